@@ -1,0 +1,504 @@
+/*
+ * soma_oracle.c -- CPU reference of the single-chain-in-mean-field (SCMF)
+ * Monte-Carlo sweep.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent, plain and slow
+ * oracle that the GPU path is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never links, imports or calls it, and it shares no code,
+ * header, table or helper with the GPU library.
+ *
+ * What it follows
+ *   Sec. 2 (Overview, SOMA paragraph): SOMA propagates a soft, coarse-grained
+ *     polymer model with the SCMF algorithm; non-bonded interactions act
+ *     through quasi-instantaneous fields, so chains move independently while
+ *     the fields stay frozen.
+ *   Sec. 2.2 (SOMA Optimization): the two dominant kernels perform trial
+ *     moves with energy evaluations, and rebuild the particle density
+ *     fields; bead coordinates are generated at initialisation.
+ *   The paper gives no formulas for the model.  The readings used here (all
+ *   stated in DESIGN.md, "Readings of the paper") are:
+ *     bonds      harmonic, E_b/kT = (k/2) sum |r_{i+1}-r_i|^2, k = 3(N-1)/Re^2
+ *     H_nb/kT    (rho0 dV / N) sum_cells f(phiA, phiB) with
+ *                Helfand form  f = (kN/2)(phiA+phiB-1)^2 - (chiN/4)(phiA-phiB)^2
+ *                or            f = chiN phiA phiB + (kN/2)(phiA+phiB-1)^2
+ *     phi_t      n_t(c) * M / B (mean of phiA+phiB is one)
+ *     omega_t    dH_nb/dn_t(c)
+ *     moves      uniform in a cube of half-width delta, Metropolis, even
+ *                beads first, then odd beads, fields frozen for the sweep
+ *     density    nearest-grid-point, cell = floor(x / cell edge) mod n
+ *     RNG        Philox4x32-10 keyed by (seed) with counter
+ *                (bead, chain, sweep, system)
+ *
+ * Position modes
+ *   0  FP64 positions (reference for observables and precision errors)
+ *   1  positions stored as FP32; all energies in FP64
+ *   2  positions stored as int32 cell + FP32 offset in [0, cell edge);
+ *      all energies in FP64
+ * Modes 1 and 2 reproduce the storage rounding of the GPU representation so
+ * that single-sweep decisions and density histograms can be compared one by
+ * one; they take every rounding step explicitly with C float arithmetic.
+ *
+ * Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off -fPIC -shared.
+ * No function here is parity-unpinned; the pins live in tests/test_oracle_*.py.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, "Parallel random       */
+/* numbers: as easy as 1, 2, 3").  Four 32-bit counter words, two key words, */
+/* ten rounds; the key is bumped by the Weyl constants between rounds.       */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += PHILOX_W0;
+        k1 += PHILOX_W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* System description                                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_chains;
+    int32_t N;
+    int32_t n_chains_a;       /* chains [0, n_chains_a) use pattern_a */
+    int32_t ham_form;         /* 0 Helfand, 1 chiN phiA phiB */
+    const uint8_t *pattern_a; /* [N]: 0 = A, 1 = B */
+    const uint8_t *pattern_b; /* [N] */
+    double chiN, kappaN, Re;
+    double box[3];
+    int32_t grid[3];
+    double move_halfwidth;
+    uint32_t sys_id;
+} orc_system;
+
+typedef struct {
+    int32_t mode;    /* 0, 1 or 2 (see header) */
+    double *x;       /* mode 0: [3][B] */
+    float *xf;       /* mode 1: [3][B] */
+    int32_t *cell;   /* mode 2: [3][B] */
+    float *off;      /* mode 2: [3][B] */
+} orc_state;
+
+static int64_t n_beads(const orc_system *s) { return (int64_t)s->n_chains * s->N; }
+static int64_t n_cells(const orc_system *s) { return (int64_t)s->grid[0] * s->grid[1] * s->grid[2]; }
+
+static int bead_type(const orc_system *s, int64_t chain, int i)
+{
+    return chain < s->n_chains_a ? s->pattern_a[i] : s->pattern_b[i];
+}
+
+static double cell_edge(const orc_system *s, int d) { return s->box[d] / (double)s->grid[d]; }
+
+/* Spring constant in kT/Re^2: the Boltzmann weight of a harmonic bond with
+ * k = 3(N-1)/Re^2 gives bond components N(0, Re^2/(3(N-1))), hence
+ * <Re^2> = Re^2 for the ideal chain. */
+static double spring_k(const orc_system *s) { return 3.0 * (double)(s->N - 1) / (s->Re * s->Re); }
+
+/* ------------------------------------------------------------------------ */
+/* Positions in FP64 from the stored representation                          */
+/* ------------------------------------------------------------------------ */
+static double get_pos(const orc_system *s, const orc_state *st, int d, int64_t b)
+{
+    int64_t B = n_beads(s);
+    switch (st->mode) {
+    case 0: return st->x[d * B + b];
+    case 1: return (double)st->xf[d * B + b];
+    default: {
+        float edge = (float)cell_edge(s, d);
+        return (double)st->cell[d * B + b] * (double)edge + (double)st->off[d * B + b];
+    }
+    }
+}
+
+/* Mode 2 renormalisation: keep the offset in [0, edge) by moving whole
+ * cells.  Every step is one FP32 rounding, and an offset that rounds up to
+ * exactly one edge goes to offset 0 of the next cell. */
+static void renorm_cell(int32_t *c, float *o, float edge)
+{
+    while (*o < 0.0f) { *o = *o + edge; *c -= 1; }
+    while (*o >= edge) { *o = *o - edge; *c += 1; }
+}
+
+/* Quantise FP64 positions into the state's representation. */
+void orc_set_positions(const orc_system *s, orc_state *st, const double *xyz)
+{
+    int64_t B = n_beads(s);
+    for (int d = 0; d < 3; ++d) {
+        float edge = (float)cell_edge(s, d);
+        for (int64_t b = 0; b < B; ++b) {
+            double x = xyz[d * B + b];
+            if (st->mode == 0) {
+                st->x[d * B + b] = x;
+            } else if (st->mode == 1) {
+                st->xf[d * B + b] = (float)x;
+            } else {
+                double c = floor(x / (double)edge);
+                int32_t ci = (int32_t)c;
+                float o = (float)(x - c * (double)edge);
+                renorm_cell(&ci, &o, edge);
+                st->cell[d * B + b] = ci;
+                st->off[d * B + b] = o;
+            }
+        }
+    }
+}
+
+void orc_get_positions(const orc_system *s, const orc_state *st, double *xyz)
+{
+    int64_t B = n_beads(s);
+    for (int d = 0; d < 3; ++d)
+        for (int64_t b = 0; b < B; ++b)
+            xyz[d * B + b] = get_pos(s, st, d, b);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nearest-grid-point cell of a bead (unwrapped coordinates, periodic box)   */
+/* ------------------------------------------------------------------------ */
+static int64_t wrap_index(int64_t i, int64_t n)
+{
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+static int64_t cell_of(const orc_system *s, const orc_state *st, int64_t b)
+{
+    int64_t B = n_beads(s);
+    int64_t idx[3];
+    for (int d = 0; d < 3; ++d) {
+        int64_t i;
+        if (st->mode == 2)
+            i = st->cell[d * B + b];
+        else
+            i = (int64_t)floor(get_pos(s, st, d, b) / cell_edge(s, d));
+        idx[d] = wrap_index(i, s->grid[d]);
+    }
+    return (idx[0] * s->grid[1] + idx[1]) * s->grid[2] + idx[2];
+}
+
+/* Density histogram: counts[t * M + cell] = number of type-t beads in cell. */
+void orc_density(const orc_system *s, const orc_state *st, uint32_t *counts)
+{
+    int64_t M = n_cells(s);
+    memset(counts, 0, sizeof(uint32_t) * 2 * (size_t)M);
+    for (int64_t c = 0; c < s->n_chains; ++c)
+        for (int i = 0; i < s->N; ++i) {
+            int64_t b = c * s->N + i;
+            counts[(int64_t)bead_type(s, c, i) * M + cell_of(s, st, b)] += 1u;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Non-bonded free energy and the quasi-instantaneous fields                 */
+/* ------------------------------------------------------------------------ */
+static double f_nb(const orc_system *s, double pa, double pb)
+{
+    double inc = pa + pb - 1.0;
+    if (s->ham_form == 1)
+        return s->chiN * pa * pb + 0.5 * s->kappaN * inc * inc;
+    return 0.5 * s->kappaN * inc * inc - 0.25 * s->chiN * (pa - pb) * (pa - pb);
+}
+
+/* H_nb / kT of the whole system from the counts. */
+double orc_energy_nb(const orc_system *s, const uint32_t *counts)
+{
+    int64_t M = n_cells(s);
+    double B = (double)n_beads(s);
+    double phi_per_count = (double)M / B;
+    double sum = 0.0, comp = 0.0;   /* Neumaier */
+    for (int64_t c = 0; c < M; ++c) {
+        double v = f_nb(s, counts[c] * phi_per_count, counts[M + c] * phi_per_count);
+        double t = sum + v;
+        if (fabs(sum) >= fabs(v)) comp += (sum - t) + v; else comp += (v - t) + sum;
+        sum = t;
+    }
+    return (B / (double)M) / (double)s->N * (sum + comp);
+}
+
+/* omega[t * M + c] = dH_nb/dn_t(c) in kT. */
+void orc_fields(const orc_system *s, const uint32_t *counts, double *omega)
+{
+    int64_t M = n_cells(s);
+    double phi_per_count = (double)M / (double)n_beads(s);
+    for (int64_t c = 0; c < M; ++c) {
+        double pa = counts[c] * phi_per_count, pb = counts[M + c] * phi_per_count;
+        double inc = s->kappaN * (pa + pb - 1.0);
+        double wa, wb;
+        if (s->ham_form == 1) {
+            wa = s->chiN * pb + inc;
+            wb = s->chiN * pa + inc;
+        } else {
+            wa = inc - 0.5 * s->chiN * (pa - pb);
+            wb = inc + 0.5 * s->chiN * (pa - pb);
+        }
+        omega[c] = wa / (double)s->N;
+        omega[M + c] = wb / (double)s->N;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random numbers of one trial move                                          */
+/* ------------------------------------------------------------------------ */
+/* The top 24 bits of each word are used.  Words 0-2 give the displacement
+ * d = fl32(delta * ((w >> 8) - 2^23) * 2^-23) in [-delta, delta), one FP32
+ * multiply of exact operands; word 3 gives u = (w >> 8) * 2^-24 in [0, 1). */
+static void move_draw(const orc_system *s, uint64_t seed, uint32_t sweep, int64_t chain, int i,
+                      float d[3], double *u)
+{
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)chain, sweep, s->sys_id};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    float delta = (float)s->move_halfwidth;
+    for (int k = 0; k < 3; ++k) {
+        float t = (float)((int32_t)(w[k] >> 8) - 8388608) * 0x1p-23f;
+        d[k] = delta * t;
+    }
+    *u = (double)((float)(w[3] >> 8) * 0x1p-24f);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One MC sweep with frozen fields                                           */
+/* ------------------------------------------------------------------------ */
+/* omega: [2][M] fields, read only during the sweep.  accepted: optional
+ * per-bead decisions (1 accepted, 0 rejected).  Returns accepted count. */
+uint64_t orc_sweep(const orc_system *s, orc_state *st, uint64_t seed, uint32_t sweep,
+                   const double *omega, uint8_t *accepted)
+{
+    const int64_t B = n_beads(s), M = n_cells(s);
+    const int N = s->N;
+    const double k = spring_k(s);
+    uint64_t n_acc = 0;
+
+    for (int parity = 0; parity < 2; ++parity) {
+#pragma omp parallel for schedule(static) reduction(+ : n_acc)
+        for (int64_t c = 0; c < s->n_chains; ++c) {
+            for (int i = parity; i < N; i += 2) {
+                int64_t b = c * N + i;
+                float d[3];
+                double u;
+                move_draw(s, seed, sweep, c, i, d, &u);
+
+                /* Old and proposed position in FP64, proposed state stored
+                 * in the mode's representation. */
+                double r_old[3], r_new[3];
+                float xf_new[3];
+                int32_t c_new[3];
+                float o_new[3];
+                for (int a = 0; a < 3; ++a) {
+                    r_old[a] = get_pos(s, st, a, b);
+                    if (st->mode == 0) {
+                        r_new[a] = r_old[a] + (double)d[a];
+                    } else if (st->mode == 1) {
+                        xf_new[a] = st->xf[a * B + b] + d[a];
+                        r_new[a] = (double)xf_new[a];
+                    } else {
+                        float edge = (float)cell_edge(s, a);
+                        c_new[a] = st->cell[a * B + b];
+                        o_new[a] = st->off[a * B + b] + d[a];
+                        renorm_cell(&c_new[a], &o_new[a], edge);
+                        r_new[a] = (double)c_new[a] * (double)edge + (double)o_new[a];
+                    }
+                }
+                double de[3] = {r_new[0] - r_old[0], r_new[1] - r_old[1], r_new[2] - r_old[2]};
+
+                /* Bond energy change in displacement form:
+                 * (k/2) sum_j [ |r'-r_j|^2 - |r-r_j|^2 ] = (k/2) sum_j [2 d.(r-r_j) + |d|^2]. */
+                double dE = 0.0;
+                double dd = de[0] * de[0] + de[1] * de[1] + de[2] * de[2];
+                for (int side = -1; side <= 1; side += 2) {
+                    int j = i + side;
+                    if (j < 0 || j >= N) continue;
+                    int64_t bj = c * N + j;
+                    double dot = 0.0;
+                    for (int a = 0; a < 3; ++a)
+                        dot += de[a] * (r_old[a] - get_pos(s, st, a, bj));
+                    dE += 0.5 * k * (2.0 * dot + dd);
+                }
+
+                /* Field energy change: omega of the bead's type at the new
+                 * cell minus at the old cell. */
+                int t = bead_type(s, c, i);
+                int64_t cell_old = cell_of(s, st, b);
+                /* cell of the proposal: evaluate it through a temporary state */
+                int64_t idx[3];
+                for (int a = 0; a < 3; ++a) {
+                    int64_t ia;
+                    if (st->mode == 2)
+                        ia = c_new[a];
+                    else
+                        ia = (int64_t)floor(r_new[a] / cell_edge(s, a));
+                    idx[a] = wrap_index(ia, s->grid[a]);
+                }
+                int64_t cell_new = (idx[0] * s->grid[1] + idx[1]) * s->grid[2] + idx[2];
+                dE += omega[(int64_t)t * M + cell_new] - omega[(int64_t)t * M + cell_old];
+
+                int acc = u < exp(-dE);
+                if (accepted) accepted[b] = (uint8_t)acc;
+                if (acc) {
+                    n_acc += 1;
+                    for (int a = 0; a < 3; ++a) {
+                        if (st->mode == 0) {
+                            st->x[a * B + b] = r_new[a];
+                        } else if (st->mode == 1) {
+                            st->xf[a * B + b] = xf_new[a];
+                        } else {
+                            st->cell[a * B + b] = c_new[a];
+                            st->off[a * B + b] = o_new[a];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return n_acc;
+}
+
+/* Full SCMF sweeps: moves with frozen fields, then the density histogram,
+ * then the field refresh.  counts [2][M] and omega [2][M] must hold the
+ * current state on entry and hold it again on return.  If refresh is zero
+ * the fields stay frozen (external-field runs). */
+uint64_t orc_run(const orc_system *s, orc_state *st, uint64_t seed, uint32_t first_sweep,
+                 int32_t n_sweeps, uint32_t *counts, double *omega, int32_t refresh)
+{
+    uint64_t acc = 0;
+    for (int32_t k = 0; k < n_sweeps; ++k) {
+        acc += orc_sweep(s, st, seed, first_sweep + (uint32_t)k, omega, NULL);
+        orc_density(s, st, counts);
+        if (refresh) orc_fields(s, counts, omega);
+    }
+    return acc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initial configuration: Gaussian random walks                              */
+/* ------------------------------------------------------------------------ */
+/* Bead 0 uniform in the box from the top 24 bits of words 0-2; every bond
+ * component N(0, Re^2/(3(N-1))) by Box-Muller on words (0,1) and (2,3).
+ * The counter's fourth word carries the system id with the top bit set, so
+ * this stream never meets a move draw.  Written in FP64. */
+void orc_init_walks(const orc_system *s, uint64_t seed, double *xyz)
+{
+    const int64_t B = n_beads(s);
+    const double sigma = s->Re / sqrt(3.0 * (double)(s->N > 1 ? s->N - 1 : 1));
+    const double two_pi = 6.283185307179586476925286766559;
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t c = 0; c < s->n_chains; ++c) {
+        double r[3];
+        for (int i = 0; i < s->N; ++i) {
+            uint32_t ctr[4] = {(uint32_t)i, (uint32_t)c, 0u, s->sys_id | 0x80000000u};
+            uint32_t w[4];
+            orc_philox4x32_10(ctr, key, w);
+            if (i == 0) {
+                for (int a = 0; a < 3; ++a)
+                    r[a] = s->box[a] * ((double)(w[a] >> 8) * 0x1p-24);
+            } else {
+                double u1 = ((double)(w[0] >> 8) + 0.5) * 0x1p-24;
+                double u2 = (double)(w[1] >> 8) * 0x1p-24;
+                double u3 = ((double)(w[2] >> 8) + 0.5) * 0x1p-24;
+                double u4 = (double)(w[3] >> 8) * 0x1p-24;
+                double rad1 = sqrt(-2.0 * log(u1)), rad2 = sqrt(-2.0 * log(u3));
+                r[0] += sigma * rad1 * cos(two_pi * u2);
+                r[1] += sigma * rad1 * sin(two_pi * u2);
+                r[2] += sigma * rad2 * cos(two_pi * u4);
+            }
+            for (int a = 0; a < 3; ++a) xyz[a * B + c * s->N + i] = r[a];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Observables (FP64, compensated sums)                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double Re2, Re2_err, Rg2, Rg2_err, Ebond_per_chain, Enb_per_chain;
+} orc_obs;
+
+typedef struct { double s, c; } nsum;
+static void nsum_add(nsum *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v; else a->c += (v - t) + a->s;
+    a->s = t;
+}
+static double nsum_val(const nsum *a) { return a->s + a->c; }
+
+/* Neumaier's improved Kahan summation, exposed for its own pin. */
+double orc_neumaier_sum(const double *v, int64_t n)
+{
+    nsum a = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) nsum_add(&a, v[i]);
+    return nsum_val(&a);
+}
+
+/* Per-chain Re^2, Rg^2 and bond energy; per_chain may be NULL, else [3][n_chains]. */
+void orc_observables(const orc_system *s, const orc_state *st, const uint32_t *counts,
+                     orc_obs *out, double *per_chain)
+{
+    const int N = s->N;
+    const double k = spring_k(s);
+    nsum re = {0, 0}, re2 = {0, 0}, rg = {0, 0}, rg2 = {0, 0}, eb = {0, 0};
+    for (int64_t c = 0; c < s->n_chains; ++c) {
+        double r0[3], rl[3], cm[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) {
+            r0[a] = get_pos(s, st, a, c * N);
+            rl[a] = get_pos(s, st, a, c * N + N - 1);
+        }
+        double e2e = 0.0;
+        for (int a = 0; a < 3; ++a) e2e += (rl[a] - r0[a]) * (rl[a] - r0[a]);
+        for (int i = 0; i < N; ++i)
+            for (int a = 0; a < 3; ++a) cm[a] += get_pos(s, st, a, c * N + i);
+        for (int a = 0; a < 3; ++a) cm[a] /= (double)N;
+        double g = 0.0, bond = 0.0;
+        for (int i = 0; i < N; ++i)
+            for (int a = 0; a < 3; ++a) {
+                double v = get_pos(s, st, a, c * N + i) - cm[a];
+                g += v * v;
+                if (i + 1 < N) {
+                    double bv = get_pos(s, st, a, c * N + i + 1) - get_pos(s, st, a, c * N + i);
+                    bond += bv * bv;
+                }
+            }
+        g /= (double)N;
+        bond *= 0.5 * k;
+        nsum_add(&re, e2e); nsum_add(&re2, e2e * e2e);
+        nsum_add(&rg, g); nsum_add(&rg2, g * g);
+        nsum_add(&eb, bond);
+        if (per_chain) {
+            per_chain[c] = e2e;
+            per_chain[s->n_chains + c] = g;
+            per_chain[2 * s->n_chains + c] = bond;
+        }
+    }
+    double n = (double)s->n_chains;
+    double mre = nsum_val(&re) / n, mrg = nsum_val(&rg) / n;
+    double vre = nsum_val(&re2) / n - mre * mre, vrg = nsum_val(&rg2) / n - mrg * mrg;
+    out->Re2 = mre;
+    out->Re2_err = sqrt(fmax(vre, 0.0) / n);
+    out->Rg2 = mrg;
+    out->Rg2_err = sqrt(fmax(vrg, 0.0) / n);
+    out->Ebond_per_chain = nsum_val(&eb) / n;
+    out->Enb_per_chain = counts ? orc_energy_nb(s, counts) / n : 0.0;
+}
