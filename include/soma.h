@@ -1,0 +1,204 @@
+/*
+ * soma.h -- C-ABI of the MI355X single-chain-in-mean-field (SCMF)
+ * Monte-Carlo sweep library (libsoma_mi355x.so, HIP for gfx950).
+ *
+ * The method (Sec. 2, SOMA paragraph, and Sec. 2.2 of the paper): soft,
+ * coarse-grained polymer chains are propagated by Monte-Carlo moves; the
+ * non-bonded interactions act through quasi-instantaneous fields that stay
+ * frozen while all chains move, so chains move independently.  One sweep is
+ *   1. a Metropolis trial move of every bead (harmonic bonds plus the field
+ *      of its type in its grid cell), even beads first, then odd beads;
+ *   2. the nearest-grid-point (NGP) density histogram of every species;
+ *   3. the field refresh from the new densities with chiN and kappaN.
+ * The paper states the model in words only; the formulas used are:
+ *   bonds    E_b/kT = (k/2) sum_i |r_{i+1} - r_i|^2, k = 3(N-1)/Re^2
+ *   phi_t(c) = n_t(c) * M / B      (M cells, B beads of the system)
+ *   Helfand  omega_A = [kN(phiA+phiB-1) - (chiN/2)(phiA-phiB)] / N,
+ *            omega_B = [kN(phiA+phiB-1) + (chiN/2)(phiA-phiB)] / N
+ *   chi-AB   omega_A = [chiN phiB + kN(phiA+phiB-1)] / N, omega_B symmetric
+ *   move     r' = r + d, d uniform in [-delta, delta)^3; accept iff
+ *            u < exp(-dE) with u uniform in [0, 1)
+ *   RNG      Philox4x32-10, key = seed, counter = (bead, chain, sweep, system)
+ *   NGP      cell = floor(x / edge) mod n (unwrapped x, periodic box);
+ *            linear cell index (ix * ny + iy) * nz + iz
+ *
+ * Conventions for every call
+ *   - Every call returns an int status (soma_status); no exception or abort
+ *     crosses the ABI.  soma_last_error() gives text for the last failure.
+ *   - Host pointers are read or written before the call returns unless the
+ *     call says otherwise.  Device pointers must be in the device memory of
+ *     the context's GPU.
+ *   - Work is enqueued on the HIP stream given at creation.  Calls that
+ *     return data to the host synchronise that stream.
+ *   - Device-side failures (count overflow, non-finite field, cell index
+ *     overflow) are latched in a status word and reported by the next
+ *     synchronising call; after that the context only accepts
+ *     soma_destroy and returns SOMA_ESTATE otherwise.
+ *   - One context per stream; calls on one context are not thread-safe.
+ */
+#ifndef SOMA_MI355X_H
+#define SOMA_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct soma_ctx soma_ctx;
+
+typedef enum {
+    SOMA_OK = 0,
+    SOMA_EINVAL = -1,      /* invalid argument */
+    SOMA_ENOMEM = -2,      /* workspace too small */
+    SOMA_EDEVICE = -3,     /* HIP runtime error */
+    SOMA_EOVERFLOW = -4,   /* a density count exceeded its width, or a cell index left int32 range */
+    SOMA_ENONFINITE = -5,  /* a field value is not finite */
+    SOMA_ESTATE = -6       /* the context latched an earlier error */
+} soma_status;
+
+/* Position representations. */
+enum {
+    SOMA_POS_F32 = 0,      /* unwrapped FP32 coordinates, 12 B per bead */
+    SOMA_POS_CELL_F32 = 1  /* int32 unwrapped cell + FP32 offset in [0, edge), 24 B per bead */
+};
+/* Density count widths. */
+enum {
+    SOMA_COUNT_U16 = 0,    /* A and B counts packed as two uint16 in one uint32 per cell */
+    SOMA_COUNT_U32 = 1     /* uint32 A and B counts, interleaved per cell */
+};
+/* Non-bonded functional. */
+enum { SOMA_HAM_HELFAND = 0, SOMA_HAM_CHI_AB = 1 };
+
+/* One independent system.  Chains [0, n_chains_a) carry the bead types of
+ * pattern_a, chains [n_chains_a, n_chains) those of pattern_b (0 = A,
+ * 1 = B): a diblock or triblock melt sets n_chains_a = n_chains, an A/B
+ * homopolymer blend an all-A pattern_a and an all-B pattern_b.
+ * Limits: 2 <= N <= 128; grid[d] >= 1; the cell edge box[d]/grid[d] must be
+ * larger than move_halfwidth. */
+typedef struct {
+    int32_t n_chains;
+    int32_t N;                 /* beads per chain */
+    int32_t n_chains_a;
+    int32_t ham_form;          /* SOMA_HAM_* */
+    const uint8_t *pattern_a;  /* host, [N] */
+    const uint8_t *pattern_b;  /* host, [N] */
+    double chiN, kappaN;
+    double Re;                 /* end-to-end distance of the ideal chain (length unit) */
+    double box[3];             /* periodic box, Re units */
+    int32_t grid[3];           /* cells per direction */
+    double move_halfwidth;     /* delta, Re units */
+} soma_system_desc;
+
+typedef struct {
+    uint64_t seed;             /* Philox key */
+    int32_t pos_repr;          /* SOMA_POS_* */
+    int32_t count_width;       /* SOMA_COUNT_* */
+    int32_t use_graph;         /* nonzero: soma_mc_sweep replays a captured hipGraph per sweep count */
+    int32_t density_mode;      /* 0: global atomics, 1: LDS-privatised window, -1: pick by timing at create */
+    int32_t reorder_every;     /* >0: spatially sort chains every this many sweeps; 0: never */
+    int32_t waves_per_block;   /* 1..16 wave tiles per workgroup; 0: library default */
+    int32_t sys_id_base;       /* system k draws with Philox counter word sys_id_base + k (< 2^31);
+                                  a system run alone with sys_id_base = k repeats its batched run */
+    void *hip_stream;          /* hipStream_t, NULL for the null stream */
+} soma_options;
+
+typedef struct {
+    double Re2, Re2_err;       /* mean |r_{N-1} - r_0|^2 over chains and its standard error */
+    double Rg2, Rg2_err;       /* mean radius of gyration squared and its standard error */
+    double Ebond_per_chain;    /* (k/2) sum |b|^2 per chain, kT */
+    double Enb_per_chain;      /* H_nb/kT per chain from the current counts */
+    double accept_ratio;       /* accepted / attempted moves since creation */
+    uint64_t n_moves, n_accepted;
+    uint64_t sweep;            /* sweeps done since creation */
+} soma_obs;
+
+typedef struct {
+    int32_t n_systems;
+    int32_t n_tiles;           /* wave tiles per sweep launch */
+    int64_t n_beads;           /* sum over systems */
+    int64_t n_cells;           /* sum over systems */
+    uint64_t sweep;            /* sweeps done */
+    int64_t bytes_per_sweep;   /* algorithmic HBM bytes of one sweep (positions, counts) */
+    int32_t density_mode;      /* the variant in use */
+    int32_t waves_per_block;
+} soma_info;
+
+/* Bytes of device workspace that soma_create needs for these systems. */
+int soma_workspace_size(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
+                        size_t *bytes);
+
+/* Create a context over caller-owned device memory `workspace` (at least
+ * soma_workspace_size bytes, 256-byte aligned).  The library never frees
+ * it; it must outlive the context.  Initialises every system with Gaussian
+ * random walks (first bead uniform in the box, bond components
+ * N(0, Re^2/(3(N-1))); the init stream of Sec. 2.2 moved to the GPU), then
+ * builds the density and fields, so a sweep can follow.  Returns
+ * SOMA_EINVAL for bad descriptors, SOMA_ENOMEM for a short workspace. */
+int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
+                void *workspace, size_t workspace_bytes, soma_ctx **out);
+
+/* Release the context (not the workspace).  Synchronises its stream. */
+int soma_destroy(soma_ctx *ctx);
+
+/* Enqueue n_sweeps >= 0 full sweeps (move, density, field) of every system.
+ * Asynchronous on the context's stream. */
+int soma_mc_sweep(soma_ctx *ctx, int32_t n_sweeps);
+
+/* Wait for the stream and report latched device errors. */
+int soma_sync(soma_ctx *ctx);
+
+/* Density counts of system `sys` after the last sweep, as uint32
+ * [2][nx][ny][nz] (A then B).  dst is device memory if dst_on_device,
+ * else host memory (then the call synchronises). */
+int soma_density(soma_ctx *ctx, int32_t sys, uint32_t *dst, int32_t dst_on_device);
+
+/* Fields omega_A, omega_B of system `sys` in kT, as float [2][nx][ny][nz]:
+ * the frozen fields the next sweep will use. */
+int soma_fields(soma_ctx *ctx, int32_t sys, float *dst, int32_t dst_on_device);
+
+/* FP64 observables of system `sys` (compensated sums).  Synchronises. */
+int soma_observables(soma_ctx *ctx, int32_t sys, soma_obs *out);
+
+/* Unwrapped FP64 positions of system `sys` as host double [3][n_chains*N]
+ * (chain-major, Re units).  Synchronises. */
+int soma_get_positions(soma_ctx *ctx, int32_t sys, double *xyz);
+
+/* Set the positions of system `sys` from host double [3][n_chains*N]
+ * (finite, |x| < 2^22 cell edges; SOMA_EINVAL otherwise),
+ * rounded to the context's representation (FP32: round to nearest; cell:
+ * floor(x/edge) and the FP32 offset), then rebuild its density.  Leaves
+ * the system's frozen/unfrozen field state as it was. */
+int soma_set_positions(soma_ctx *ctx, int32_t sys, const double *xyz);
+
+/* Raw stored state of system `sys`, for exact checkpoints.
+ * SOMA_POS_F32: f32 = float [3][n_chains*N], cell = NULL.
+ * SOMA_POS_CELL_F32: cell = int32 [3][n_chains*N], f32 = float offsets
+ * [3][n_chains*N].  Host memory.  soma_set_state rebuilds the density. */
+int soma_get_state(soma_ctx *ctx, int32_t sys, float *f32, int32_t *cell);
+int soma_set_state(soma_ctx *ctx, int32_t sys, const float *f32, const int32_t *cell);
+
+/* Freeze the fields of system `sys` to host float [2][nx][ny][nz]: later
+ * sweeps move against them and still rebuild the density, but never
+ * refresh them.  Returns SOMA_ENONFINITE for a non-finite value. */
+int soma_set_fields(soma_ctx *ctx, int32_t sys, const float *omega);
+
+/* Return system `sys` to fields derived from its density each sweep. */
+int soma_release_fields(soma_ctx *ctx, int32_t sys);
+
+/* Set the sweep counter (the Philox counter word of the next sweep) for a
+ * resumed checkpoint, and rebuild every system's density for it. */
+int soma_set_sweep(soma_ctx *ctx, uint64_t sweep);
+
+int soma_get_info(soma_ctx *ctx, soma_info *out);
+
+/* Text of the last error of ctx (or of the last failed soma_create when
+ * ctx is NULL).  Valid until the next call on the context. */
+const char *soma_last_error(const soma_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOMA_MI355X_H */

@@ -1,0 +1,783 @@
+// soma_capi.cpp -- host runtime and C-ABI of libsoma_mi355x (see include/soma.h).
+//
+// The runtime owns the context: the system table, the wave-tile table, the
+// carving of the caller's workspace, the graph cache and the error latch.
+// Every step of the sweep runs in the HIP kernels of soma_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "soma.h"
+#include "soma_launch.hpp"
+#include "soma_types.hpp"
+
+using soma::DevSys;
+using soma::Tile;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Layout {
+    size_t systems, tiles, chain_id, P[3], C[3], counts, omega, accept, status, partials, obs_out,
+        staging, total;
+    int64_t total_slots = 0, total_cells = 0, total_chains = 0, count_words = 0;
+    int n_tiles = 0;
+    int64_t max_obs_blocks = 0, max_cells = 0;
+};
+
+struct HostSys {
+    soma_system_desc d;
+    std::vector<uint8_t> pa, pb;
+    DevSys dev;
+    int tile_begin, tile_end;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+inline int64_t align64(int64_t v) { return (v + 63) & ~int64_t(63); }
+
+}  // namespace
+
+struct soma_ctx {
+    soma_options opt{};
+    std::vector<HostSys> sys;
+    std::vector<Tile> tiles;
+    Layout L;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int repr = 0, cw = 0, waves_per_block = 4, xcd_remap = 1, density_mode = 0;
+    uint64_t sweep = 0;
+    int latched = SOMA_OK;
+    std::string err;
+    std::map<int, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_defs;
+
+    DevSys *d_sys() const { return reinterpret_cast<DevSys *>(ws + L.systems); }
+    Tile *d_tiles() const { return reinterpret_cast<Tile *>(ws + L.tiles); }
+    float *P(int d) const { return reinterpret_cast<float *>(ws + L.P[d]); }
+    int *C(int d) const { return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + L.C[d]) : nullptr; }
+    uint32_t *counts() const { return reinterpret_cast<uint32_t *>(ws + L.counts); }
+    uint32_t *counts_buf(uint64_t s) const { return counts() + (s % 3) * L.count_words; }
+    float2 *omega() const { return reinterpret_cast<float2 *>(ws + L.omega); }
+    unsigned long long *accept() const { return reinterpret_cast<unsigned long long *>(ws + L.accept); }
+    uint32_t *status() const { return reinterpret_cast<uint32_t *>(ws + L.status); }
+    uint64_t *sweep_ctr() const { return reinterpret_cast<uint64_t *>(ws + L.status + 8); }
+    double *partials() const { return reinterpret_cast<double *>(ws + L.partials); }
+    double *obs_out() const { return reinterpret_cast<double *>(ws + L.obs_out); }
+    void *staging() const { return ws + L.staging; }
+    int64_t words_per_cell() const { return cw == soma::COUNT_U16 ? 1 : 2; }
+};
+
+namespace {
+
+int fail(soma_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+int hip_fail(soma_ctx *c, hipError_t e, const char *where)
+{
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    if (c) c->latched = SOMA_EDEVICE;
+    return fail(c, SOMA_EDEVICE, m);
+}
+
+#define HIPCHK(ctx, expr)                                    \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt, std::string &msg)
+{
+    if (!sys || !opt) { msg = "null descriptor or options"; return SOMA_EINVAL; }
+    if (n_sys < 1 || n_sys >= (1 << 30)) { msg = "n_sys out of range"; return SOMA_EINVAL; }
+    if (opt->pos_repr != SOMA_POS_F32 && opt->pos_repr != SOMA_POS_CELL_F32) { msg = "bad pos_repr"; return SOMA_EINVAL; }
+    if (opt->count_width != SOMA_COUNT_U16 && opt->count_width != SOMA_COUNT_U32) { msg = "bad count_width"; return SOMA_EINVAL; }
+    if (opt->waves_per_block < 0 || opt->waves_per_block > 16) { msg = "waves_per_block must be 0..16"; return SOMA_EINVAL; }
+    if (opt->density_mode < -1 || opt->density_mode > 1) { msg = "density_mode must be -1, 0 or 1"; return SOMA_EINVAL; }
+    if (opt->reorder_every < 0) { msg = "reorder_every must be >= 0"; return SOMA_EINVAL; }
+    if (opt->sys_id_base < 0 || (int64_t)opt->sys_id_base + n_sys >= (int64_t(1) << 31)) { msg = "sys_id_base + n_sys must stay below 2^31"; return SOMA_EINVAL; }
+    for (int32_t k = 0; k < n_sys; ++k) {
+        const soma_system_desc &d = sys[k];
+        char b[160];
+        auto bad = [&](const char *what) { std::snprintf(b, sizeof b, "system %d: %s", k, what); msg = b; return SOMA_EINVAL; };
+        if (d.n_chains < 1) return bad("n_chains must be >= 1");
+        if (d.N < 2 || d.N > soma::kMaxN) return bad("N must be in [2, 128]");
+        if (d.n_chains_a < 0 || d.n_chains_a > d.n_chains) return bad("n_chains_a out of range");
+        if (d.ham_form != SOMA_HAM_HELFAND && d.ham_form != SOMA_HAM_CHI_AB) return bad("bad ham_form");
+        if (d.n_chains_a > 0 && !d.pattern_a) return bad("pattern_a is null");
+        if (d.n_chains_a < d.n_chains && !d.pattern_b) return bad("pattern_b is null");
+        for (int i = 0; i < d.N; ++i) {
+            if (d.n_chains_a > 0 && d.pattern_a[i] > 1) return bad("pattern_a entries must be 0 or 1");
+            if (d.n_chains_a < d.n_chains && d.pattern_b[i] > 1) return bad("pattern_b entries must be 0 or 1");
+        }
+        if (!std::isfinite(d.chiN) || !std::isfinite(d.kappaN)) return bad("chiN/kappaN not finite");
+        if (!(d.Re > 0) || !std::isfinite(d.Re)) return bad("Re must be > 0");
+        int64_t cells = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (!(d.box[a] > 0) || !std::isfinite(d.box[a])) return bad("box must be > 0");
+            if (d.grid[a] < 1 || d.grid[a] > (1 << 15)) return bad("grid must be in [1, 32768]");
+            cells *= d.grid[a];
+            const double edge = d.box[a] / d.grid[a];
+            if (!(d.move_halfwidth > 0) || !(d.move_halfwidth < edge)) return bad("move_halfwidth must be in (0, cell edge)");
+        }
+        if (cells >= (int64_t(1) << 31)) return bad("too many cells");
+    }
+    return SOMA_OK;
+}
+
+Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt, std::vector<HostSys> *out)
+{
+    Layout L{};
+    int64_t slots = 0, cells = 0, chains = 0;
+    int tiles = 0;
+    int64_t max_blocks = 1, max_cells = 1;
+    for (int32_t k = 0; k < n_sys; ++k) {
+        const soma_system_desc &d = sys[k];
+        const int P = (d.N + 1) / 2, G = soma::kWave / P;
+        const int64_t M = (int64_t)d.grid[0] * d.grid[1] * d.grid[2];
+        const int nt = (d.n_chains + G - 1) / G;
+        if (out) {
+            HostSys h{};
+            h.d = d;
+            h.pa.assign(d.N, 0);
+            h.pb.assign(d.N, 0);
+            if (d.n_chains_a > 0) std::memcpy(h.pa.data(), d.pattern_a, d.N);
+            if (d.n_chains_a < d.n_chains) std::memcpy(h.pb.data(), d.pattern_b, d.N);
+            h.d.pattern_a = nullptr;
+            h.d.pattern_b = nullptr;
+            DevSys &v = h.dev;
+            std::memset(&v, 0, sizeof v);
+            v.slot_off = slots;
+            v.cell_off = cells;
+            v.chain_off = chains;
+            v.n_chains = d.n_chains;
+            v.N = d.N;
+            v.P = P;
+            v.G = G;
+            v.n_chains_a = d.n_chains_a;
+            v.sys_id = (uint32_t)(opt->sys_id_base + k);
+            v.frozen = 0;
+            for (int a = 0; a < 3; ++a) {
+                v.n[a] = d.grid[a];
+                v.inv_n[a] = (float)(1.0 / d.grid[a]);
+                v.edge[a] = (float)(d.box[a] / d.grid[a]);
+                v.inv_edge[a] = (float)(1.0 / (double)v.edge[a]);
+            }
+            const double k_spring = 3.0 * (d.N - 1) / (d.Re * d.Re);
+            v.k_half = (float)(0.5 * k_spring);
+            v.delta = (float)d.move_halfwidth;
+            const double s = (double)M / ((double)d.n_chains * d.N);   // phi per count
+            const double inv_n = 1.0 / d.N;
+            if (d.ham_form == SOMA_HAM_HELFAND) {
+                v.cAA = (float)(s * (d.kappaN - 0.5 * d.chiN) * inv_n);
+                v.cAB = (float)(s * (d.kappaN + 0.5 * d.chiN) * inv_n);
+                v.cBA = v.cAB;
+                v.cBB = v.cAA;
+            } else {
+                v.cAA = (float)(s * d.kappaN * inv_n);
+                v.cAB = (float)(s * (d.kappaN + d.chiN) * inv_n);
+                v.cBA = v.cAB;
+                v.cBB = v.cAA;
+            }
+            v.c0 = (float)(-d.kappaN * inv_n);
+            v.n_cells = M;
+            for (int i = 0; i < d.N; ++i) {
+                if (h.pa[i]) v.pat_a[i >> 5] |= 1u << (i & 31);
+                if (h.pb[i]) v.pat_b[i >> 5] |= 1u << (i & 31);
+            }
+            h.tile_begin = tiles;
+            h.tile_end = tiles + nt;
+            out->push_back(std::move(h));
+        }
+        slots = align64(slots + (int64_t)d.n_chains * 2 * P);
+        cells = align64(cells + M);
+        chains += d.n_chains;
+        tiles += nt;
+        max_blocks = std::max<int64_t>(max_blocks, (d.n_chains + 255) / 256 + (M + 255) / 256);
+        max_cells = std::max<int64_t>(max_cells, M);
+    }
+    const bool cell = opt->pos_repr == SOMA_POS_CELL_F32;
+    L.total_slots = slots;
+    L.total_cells = cells;
+    L.total_chains = chains;
+    L.n_tiles = tiles;
+    L.count_words = cells * (opt->count_width == SOMA_COUNT_U16 ? 1 : 2);
+    L.max_obs_blocks = max_blocks;
+    L.max_cells = max_cells;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    L.systems = take(sizeof(DevSys) * n_sys);
+    L.tiles = take(sizeof(Tile) * tiles);
+    L.chain_id = take(sizeof(uint32_t) * chains);
+    for (int a = 0; a < 3; ++a) L.P[a] = take(sizeof(float) * slots);
+    for (int a = 0; a < 3; ++a) L.C[a] = cell ? take(sizeof(int) * slots) : 0;
+    L.counts = take(sizeof(uint32_t) * 3 * L.count_words);
+    L.omega = take(sizeof(float) * 2 * cells);
+    L.accept = take(sizeof(uint64_t) * n_sys);
+    L.status = take(64);
+    L.partials = take(sizeof(double) * 12 * max_blocks);
+    L.obs_out = take(sizeof(double) * 8);
+    L.staging = take(sizeof(float) * 2 * max_cells);
+    L.total = off;
+    return L;
+}
+
+int check_ctx(soma_ctx *c)
+{
+    if (!c) return SOMA_EINVAL;
+    if (c->latched != SOMA_OK) return fail(c, SOMA_ESTATE, "context latched an earlier error: " + c->err);
+    return SOMA_OK;
+}
+
+int check_sys(soma_ctx *c, int32_t sys)
+{
+    if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(c, SOMA_EINVAL, "system index out of range");
+    return SOMA_OK;
+}
+
+// Synchronise and turn latched device status bits into an error code.
+int sync_status(soma_ctx *c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    uint32_t st = 0;
+    HIPCHK(c, hipMemcpy(&st, c->status(), sizeof st, hipMemcpyDeviceToHost));
+    if (st & soma::ST_COUNT_OVERFLOW) { c->latched = SOMA_EOVERFLOW; return fail(c, SOMA_EOVERFLOW, "density count exceeded its width"); }
+    if (st & soma::ST_CELL_OVERFLOW) { c->latched = SOMA_EOVERFLOW; return fail(c, SOMA_EOVERFLOW, "bead cell index left the int32 range (or a coordinate is not finite)"); }
+    if (st & soma::ST_NONFINITE) { c->latched = SOMA_ENONFINITE; return fail(c, SOMA_ENONFINITE, "non-finite field value"); }
+    return SOMA_OK;
+}
+
+soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
+{
+    soma::SweepArgs a{};
+    a.systems = c->d_sys();
+    a.tiles = c->d_tiles();
+    a.n_tiles = c->L.n_tiles;
+    a.waves_per_block = c->waves_per_block;
+    a.xcd_remap = c->xcd_remap;
+    a.chain_id = nullptr;
+    for (int d = 0; d < 3; ++d) {
+        (&a.P0)[d] = c->P(d);
+        (&a.C0)[d] = c->C(d);
+    }
+    a.counts = c->counts();
+    a.count_words = c->L.count_words;
+    a.omega = c->omega();
+    a.sweep_ctr = c->sweep_ctr();
+    a.rel = rel;
+    a.seed = c->opt.seed;
+    a.accept = c->accept();
+    a.status = c->status();
+    return a;
+}
+
+// Rebuild the density of one system (or all when sys < 0) into the current buffer.
+int rebuild_density(soma_ctx *c, int32_t sys)
+{
+    uint32_t *cur = c->counts_buf(c->sweep);
+    const int64_t wpc = c->words_per_cell();
+    int tb = 0, te = c->L.n_tiles;
+    if (sys < 0) {
+        HIPCHK(c, soma::launch_fill_u32(cur, c->L.count_words, 0u, c->stream));
+    } else {
+        const HostSys &h = c->sys[sys];
+        HIPCHK(c, soma::launch_fill_u32(cur + h.dev.cell_off * wpc, h.dev.n_cells * wpc, 0u, c->stream));
+        tb = h.tile_begin;
+        te = h.tile_end;
+    }
+    soma::DensityArgs d{};
+    d.systems = c->d_sys();
+    d.tiles = c->d_tiles();
+    d.tile_begin = tb;
+    d.tile_end = te;
+    for (int k = 0; k < 3; ++k) {
+        (&d.P0)[k] = c->P(k);
+        (&d.C0)[k] = c->C(k);
+    }
+    d.counts = cur;
+    d.status = c->status();
+    HIPCHK(c, soma::launch_density(c->repr, c->cw, d, c->stream));
+    return SOMA_OK;
+}
+
+int upload_sys(soma_ctx *c, int32_t sys)
+{
+    HIPCHK(c, hipMemcpyAsync(c->d_sys() + sys, &c->sys[sys].dev, sizeof(DevSys), hipMemcpyHostToDevice, c->stream));
+    return SOMA_OK;
+}
+
+int record_sweeps(soma_ctx *c, int32_t n, hipStream_t st)
+{
+    for (int32_t r = 0; r < n; ++r) {
+        soma::SweepArgs a = sweep_args(c, (uint32_t)r);
+        HIPCHK(c, soma::launch_sweep(c->repr, c->cw, a, st));
+    }
+    HIPCHK(c, soma::launch_advance(c->sweep_ctr(), (uint32_t)n, st));
+    return SOMA_OK;
+}
+
+constexpr int kGraphChunk = 256;
+
+int graph_for(soma_ctx *c, int32_t n, hipGraphExec_t *out)
+{
+    auto it = c->graphs.find(n);
+    if (it != c->graphs.end()) { *out = it->second; return SOMA_OK; }
+    if (!c->capture_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    int rc = record_sweeps(c, n, c->capture_stream);
+    hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+    if (rc != SOMA_OK) return rc;
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    HIPCHK(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    c->graph_defs.push_back(g);
+    c->graphs[n] = ex;
+    *out = ex;
+    return SOMA_OK;
+}
+
+void quantise_host(const soma_ctx *c, const HostSys &h, const double *xyz, std::vector<float> (&P)[3],
+                   std::vector<int> (&Cv)[3])
+{
+    const int N = h.d.N, stride = 2 * h.dev.P;
+    const int64_t B = (int64_t)h.d.n_chains * N;
+    for (int a = 0; a < 3; ++a) {
+        P[a].assign((size_t)h.d.n_chains * stride, 0.0f);
+        if (c->repr == soma::REPR_CELL) Cv[a].assign((size_t)h.d.n_chains * stride, 0);
+        const float e = h.dev.edge[a];
+        for (int64_t ch = 0; ch < h.d.n_chains; ++ch)
+            for (int i = 0; i < N; ++i) {
+                const double x = xyz[a * B + ch * N + i];
+                const size_t s = (size_t)(ch * stride + i);
+                if (c->repr == soma::REPR_F32) {
+                    P[a][s] = (float)x;
+                } else {
+                    const double cf = std::floor(x / (double)e);
+                    int ci = (int)cf;
+                    float o = (float)(x - cf * (double)e);
+                    while (o < 0.0f) { o = o + e; ci -= 1; }
+                    while (o >= e) { o = o - e; ci += 1; }
+                    Cv[a][s] = ci;
+                    P[a][s] = o;
+                }
+            }
+    }
+}
+
+int download_slots(soma_ctx *c, const HostSys &h, std::vector<float> (&P)[3], std::vector<int> (&Cv)[3])
+{
+    const size_t n = (size_t)h.d.n_chains * 2 * h.dev.P;
+    for (int a = 0; a < 3; ++a) {
+        P[a].resize(n);
+        HIPCHK(c, hipMemcpyAsync(P[a].data(), c->P(a) + h.dev.slot_off, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        if (c->repr == soma::REPR_CELL) {
+            Cv[a].resize(n);
+            HIPCHK(c, hipMemcpyAsync(Cv[a].data(), c->C(a) + h.dev.slot_off, n * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SOMA_OK;
+}
+
+int upload_slots(soma_ctx *c, const HostSys &h, const std::vector<float> (&P)[3], const std::vector<int> (&Cv)[3])
+{
+    const size_t n = (size_t)h.d.n_chains * 2 * h.dev.P;
+    for (int a = 0; a < 3; ++a) {
+        HIPCHK(c, hipMemcpyAsync(c->P(a) + h.dev.slot_off, P[a].data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        if (c->repr == soma::REPR_CELL)
+            HIPCHK(c, hipMemcpyAsync(c->C(a) + h.dev.slot_off, Cv[a].data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    }
+    // host vectors must stay alive until the copies complete
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SOMA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int soma_workspace_size(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt, size_t *bytes)
+{
+    std::string msg;
+    int rc = validate(sys, n_sys, opt, msg);
+    if (rc != SOMA_OK) return fail(nullptr, rc, msg);
+    if (!bytes) return fail(nullptr, SOMA_EINVAL, "bytes is null");
+    *bytes = plan(sys, n_sys, opt, nullptr).total;
+    return SOMA_OK;
+}
+
+int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt, void *workspace,
+                size_t workspace_bytes, soma_ctx **out)
+{
+    std::string msg;
+    if (!out) return fail(nullptr, SOMA_EINVAL, "out is null");
+    *out = nullptr;
+    int rc = validate(sys, n_sys, opt, msg);
+    if (rc != SOMA_OK) return fail(nullptr, rc, msg);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return fail(nullptr, SOMA_EINVAL, "workspace must be non-null and 256-byte aligned");
+    soma_ctx *c = new (std::nothrow) soma_ctx();
+    if (!c) return fail(nullptr, SOMA_ENOMEM, "host allocation failed");
+    c->opt = *opt;
+    c->repr = opt->pos_repr == SOMA_POS_CELL_F32 ? soma::REPR_CELL : soma::REPR_F32;
+    c->cw = opt->count_width == SOMA_COUNT_U32 ? soma::COUNT_U32 : soma::COUNT_U16;
+    c->waves_per_block = opt->waves_per_block > 0 ? opt->waves_per_block : 4;
+    c->density_mode = 0;
+    c->stream = reinterpret_cast<hipStream_t>(opt->hip_stream);
+    c->L = plan(sys, n_sys, opt, &c->sys);
+    if (workspace_bytes < c->L.total) {
+        char b[128];
+        std::snprintf(b, sizeof b, "workspace has %zu bytes, needs %zu", workspace_bytes, c->L.total);
+        delete c;
+        return fail(nullptr, SOMA_ENOMEM, b);
+    }
+    c->ws = static_cast<char *>(workspace);
+    for (size_t k = 0; k < c->sys.size(); ++k) {
+        const HostSys &h = c->sys[k];
+        for (int t = h.tile_begin; t < h.tile_end; ++t)
+            c->tiles.push_back(Tile{(uint32_t)k, (uint32_t)((t - h.tile_begin) * h.dev.G)});
+    }
+    auto bail = [&](int code) { g_create_error = c->err; soma_destroy(c); return code; };
+    std::vector<DevSys> dv;
+    for (const HostSys &h : c->sys) dv.push_back(h.dev);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(c->d_sys(), dv.data(), sizeof(DevSys) * dv.size(), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+        return bail(hip_fail(c, e, "upload systems"));
+    if ((e = hipMemcpyAsync(c->d_tiles(), c->tiles.data(), sizeof(Tile) * c->tiles.size(), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+        return bail(hip_fail(c, e, "upload tiles"));
+    // clear counts, fields, accept counters, status and sweep counter
+    if ((rc = [&] {
+             HIPCHK(c, soma::launch_fill_u32(c->counts(), 3 * c->L.count_words, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->omega()), 2 * c->L.total_cells, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->accept()), 2 * (int64_t)n_sys, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(c->status(), 16, 0u, c->stream));
+             return (int)SOMA_OK;
+         }()) != SOMA_OK)
+        return bail(rc);
+    for (const HostSys &h : c->sys) {
+        soma::InitArgs ia{};
+        ia.repr = c->repr;
+        ia.n_chains = h.d.n_chains;
+        ia.N = h.d.N;
+        ia.stride = 2 * h.dev.P;
+        ia.slot_off = h.dev.slot_off;
+        ia.sys_id = h.dev.sys_id;
+        ia.seed = opt->seed;
+        for (int a = 0; a < 3; ++a) {
+            ia.box[a] = h.d.box[a];
+            ia.edge[a] = h.dev.edge[a];
+            (&ia.P0)[a] = c->P(a);
+            (&ia.C0)[a] = c->C(a);
+        }
+        ia.sigma = h.d.Re / std::sqrt(3.0 * (h.d.N - 1));
+        if ((e = soma::launch_init(ia, c->stream)) != hipSuccess) return bail(hip_fail(c, e, "init kernel"));
+    }
+    if ((rc = rebuild_density(c, -1)) != SOMA_OK) return bail(rc);
+    if ((rc = sync_status(c)) != SOMA_OK) return bail(rc);
+    *out = c;
+    return SOMA_OK;
+}
+
+int soma_destroy(soma_ctx *c)
+{
+    if (!c) return SOMA_EINVAL;
+    if (c->ws) (void)hipStreamSynchronize(c->stream);
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t g : c->graph_defs) (void)hipGraphDestroy(g);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    delete c;
+    return SOMA_OK;
+}
+
+int soma_mc_sweep(soma_ctx *c, int32_t n)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if (n < 0) return fail(c, SOMA_EINVAL, "n_sweeps must be >= 0");
+    if (n == 0) return SOMA_OK;
+    if (c->opt.use_graph) {
+        int32_t left = n;
+        while (left > 0) {
+            const int32_t chunk = left > kGraphChunk ? kGraphChunk : left;
+            hipGraphExec_t ex;
+            if ((rc = graph_for(c, chunk, &ex)) != SOMA_OK) return rc;
+            HIPCHK(c, hipGraphLaunch(ex, c->stream));
+            left -= chunk;
+        }
+    } else {
+        if ((rc = record_sweeps(c, n, c->stream)) != SOMA_OK) return rc;
+    }
+    c->sweep += (uint64_t)n;
+    return SOMA_OK;
+}
+
+int soma_sync(soma_ctx *c)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    return sync_status(c);
+}
+
+int soma_density(soma_ctx *c, int32_t sys, uint32_t *dst, int32_t dst_on_device)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!dst) return fail(c, SOMA_EINVAL, "dst is null");
+    const HostSys &h = c->sys[sys];
+    uint32_t *target = dst_on_device ? dst : static_cast<uint32_t *>(c->staging());
+    HIPCHK(c, soma::launch_unpack_counts(c->cw, c->counts_buf(c->sweep), h.dev.cell_off, h.dev.n_cells, target, c->stream));
+    if (!dst_on_device)
+        HIPCHK(c, hipMemcpyAsync(dst, target, sizeof(uint32_t) * 2 * h.dev.n_cells, hipMemcpyDeviceToHost, c->stream));
+    return sync_status(c);
+}
+
+int soma_fields(soma_ctx *c, int32_t sys, float *dst, int32_t dst_on_device)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!dst) return fail(c, SOMA_EINVAL, "dst is null");
+    const HostSys &h = c->sys[sys];
+    soma::FieldArgs f{};
+    f.systems = c->d_sys();
+    f.sys = sys;
+    f.n_cells = h.dev.n_cells;
+    f.counts = c->counts_buf(c->sweep);
+    f.omega = c->omega();
+    f.out = dst_on_device ? dst : static_cast<float *>(c->staging());
+    HIPCHK(c, soma::launch_fields(c->cw, f, c->stream));
+    if (!dst_on_device)
+        HIPCHK(c, hipMemcpyAsync(dst, f.out, sizeof(float) * 2 * h.dev.n_cells, hipMemcpyDeviceToHost, c->stream));
+    return sync_status(c);
+}
+
+int soma_observables(soma_ctx *c, int32_t sys, soma_obs *out)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!out) return fail(c, SOMA_EINVAL, "out is null");
+    const HostSys &h = c->sys[sys];
+    soma::ObsArgs a{};
+    a.repr = c->repr;
+    a.n_chains = h.d.n_chains;
+    a.N = h.d.N;
+    a.stride = 2 * h.dev.P;
+    a.slot_off = h.dev.slot_off;
+    for (int d = 0; d < 3; ++d) {
+        a.edge[d] = h.dev.edge[d];
+        (&a.P0)[d] = c->P(d);
+        (&a.C0)[d] = c->C(d);
+    }
+    a.k_half = 1.5 * (h.d.N - 1) / (h.d.Re * h.d.Re);
+    a.counts = c->counts_buf(c->sweep);
+    a.cell_off = h.dev.cell_off;
+    a.n_cells = h.dev.n_cells;
+    const double B = (double)h.d.n_chains * h.d.N;
+    a.phi_per_count = (double)h.dev.n_cells / B;
+    a.chiN = h.d.chiN;
+    a.kappaN = h.d.kappaN;
+    a.ham_form = h.d.ham_form;
+    a.partials = c->partials();
+    a.block_base = 0;
+    HIPCHK(c, soma::launch_observables(c->cw, a, c->obs_out(), c->stream));
+    double q[6];
+    unsigned long long acc = 0;
+    HIPCHK(c, hipMemcpyAsync(q, c->obs_out(), sizeof q, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&acc, c->accept() + sys, sizeof acc, hipMemcpyDeviceToHost, c->stream));
+    if ((rc = sync_status(c)) != SOMA_OK) return rc;
+    const double n = (double)h.d.n_chains;
+    out->Re2 = q[0] / n;
+    out->Re2_err = std::sqrt(std::max(q[1] / n - out->Re2 * out->Re2, 0.0) / n);
+    out->Rg2 = q[2] / n;
+    out->Rg2_err = std::sqrt(std::max(q[3] / n - out->Rg2 * out->Rg2, 0.0) / n);
+    out->Ebond_per_chain = q[4] / n;
+    out->Enb_per_chain = (B / (double)h.dev.n_cells) / h.d.N * q[5] / n;
+    out->sweep = c->sweep;
+    out->n_moves = (uint64_t)(c->sweep * (uint64_t)B);
+    out->n_accepted = acc;
+    out->accept_ratio = out->n_moves ? (double)acc / (double)out->n_moves : 0.0;
+    return SOMA_OK;
+}
+
+int soma_get_positions(soma_ctx *c, int32_t sys, double *xyz)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!xyz) return fail(c, SOMA_EINVAL, "xyz is null");
+    const HostSys &h = c->sys[sys];
+    std::vector<float> P[3];
+    std::vector<int> Cv[3];
+    if ((rc = download_slots(c, h, P, Cv)) != SOMA_OK) return rc;
+    const int N = h.d.N, stride = 2 * h.dev.P;
+    const int64_t B = (int64_t)h.d.n_chains * N;
+    for (int a = 0; a < 3; ++a)
+        for (int64_t ch = 0; ch < h.d.n_chains; ++ch)
+            for (int i = 0; i < N; ++i) {
+                const size_t s = (size_t)(ch * stride + i);
+                xyz[a * B + ch * N + i] = c->repr == soma::REPR_F32
+                                              ? (double)P[a][s]
+                                              : (double)Cv[a][s] * (double)h.dev.edge[a] + (double)P[a][s];
+            }
+    return sync_status(c);
+}
+
+int soma_set_positions(soma_ctx *c, int32_t sys, const double *xyz)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!xyz) return fail(c, SOMA_EINVAL, "xyz is null");
+    const HostSys &h = c->sys[sys];
+    const int64_t B = (int64_t)h.d.n_chains * h.d.N;
+    for (int a = 0; a < 3; ++a)
+        for (int64_t i = 0; i < B; ++i) {
+            const double v = xyz[a * B + i];
+            if (!std::isfinite(v) || std::fabs(v) >= 4194304.0 * (double)h.dev.edge[a])
+                return fail(c, SOMA_EINVAL, "positions must be finite and within 2^22 cells of the origin");
+        }
+    std::vector<float> P[3];
+    std::vector<int> Cv[3];
+    quantise_host(c, h, xyz, P, Cv);
+    if ((rc = upload_slots(c, h, P, Cv)) != SOMA_OK) return rc;
+    if ((rc = rebuild_density(c, sys)) != SOMA_OK) return rc;
+    return sync_status(c);
+}
+
+int soma_get_state(soma_ctx *c, int32_t sys, float *f32, int32_t *cell)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!f32 || (c->repr == soma::REPR_CELL && !cell)) return fail(c, SOMA_EINVAL, "null state buffer");
+    const HostSys &h = c->sys[sys];
+    std::vector<float> P[3];
+    std::vector<int> Cv[3];
+    if ((rc = download_slots(c, h, P, Cv)) != SOMA_OK) return rc;
+    const int N = h.d.N, stride = 2 * h.dev.P;
+    const int64_t B = (int64_t)h.d.n_chains * N;
+    for (int a = 0; a < 3; ++a)
+        for (int64_t ch = 0; ch < h.d.n_chains; ++ch)
+            for (int i = 0; i < N; ++i) {
+                const size_t s = (size_t)(ch * stride + i);
+                f32[a * B + ch * N + i] = P[a][s];
+                if (c->repr == soma::REPR_CELL) cell[a * B + ch * N + i] = Cv[a][s];
+            }
+    return sync_status(c);
+}
+
+int soma_set_state(soma_ctx *c, int32_t sys, const float *f32, const int32_t *cell)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!f32 || (c->repr == soma::REPR_CELL && !cell)) return fail(c, SOMA_EINVAL, "null state buffer");
+    const HostSys &h = c->sys[sys];
+    const int N = h.d.N, stride = 2 * h.dev.P;
+    const int64_t B = (int64_t)h.d.n_chains * N;
+    std::vector<float> P[3];
+    std::vector<int> Cv[3];
+    for (int a = 0; a < 3; ++a) {
+        P[a].assign((size_t)h.d.n_chains * stride, 0.0f);
+        if (c->repr == soma::REPR_CELL) Cv[a].assign((size_t)h.d.n_chains * stride, 0);
+        for (int64_t ch = 0; ch < h.d.n_chains; ++ch)
+            for (int i = 0; i < N; ++i) {
+                const size_t s = (size_t)(ch * stride + i);
+                const float v = f32[a * B + ch * N + i];
+                if (!std::isfinite(v)) return fail(c, SOMA_EINVAL, "state values must be finite");
+                if (c->repr == soma::REPR_CELL) {
+                    const int cv = cell[a * B + ch * N + i];
+                    if (!(v >= 0.0f && v < h.dev.edge[a])) return fail(c, SOMA_EINVAL, "offsets must lie in [0, edge)");
+                    if (cv <= -(1 << 22) || cv >= (1 << 22)) return fail(c, SOMA_EINVAL, "cell index out of range (|cell| < 2^22)");
+                    Cv[a][s] = cv;
+                }
+                P[a][s] = v;
+            }
+    }
+    if ((rc = upload_slots(c, h, P, Cv)) != SOMA_OK) return rc;
+    if ((rc = rebuild_density(c, sys)) != SOMA_OK) return rc;
+    return sync_status(c);
+}
+
+int soma_set_fields(soma_ctx *c, int32_t sys, const float *omega)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!omega) return fail(c, SOMA_EINVAL, "omega is null");
+    HostSys &h = c->sys[sys];
+    const int64_t M = h.dev.n_cells;
+    std::vector<float2> w((size_t)M);
+    for (int64_t i = 0; i < M; ++i) {
+        if (!std::isfinite(omega[i]) || !std::isfinite(omega[M + i])) return fail(c, SOMA_ENONFINITE, "omega has a non-finite value");
+        w[(size_t)i] = make_float2(omega[i], omega[M + i]);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->omega() + h.dev.cell_off, w.data(), sizeof(float2) * M, hipMemcpyHostToDevice, c->stream));
+    h.dev.frozen = 1;
+    if ((rc = upload_sys(c, sys)) != SOMA_OK) return rc;
+    return sync_status(c);
+}
+
+int soma_release_fields(soma_ctx *c, int32_t sys)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    c->sys[sys].dev.frozen = 0;
+    if ((rc = upload_sys(c, sys)) != SOMA_OK) return rc;
+    return sync_status(c);
+}
+
+int soma_set_sweep(soma_ctx *c, uint64_t sweep)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->sweep_ctr(), &sweep, sizeof sweep, hipMemcpyHostToDevice));
+    c->sweep = sweep;
+    HIPCHK(c, soma::launch_fill_u32(c->counts(), 3 * c->L.count_words, 0u, c->stream));
+    if ((rc = rebuild_density(c, -1)) != SOMA_OK) return rc;
+    return sync_status(c);
+}
+
+int soma_get_info(soma_ctx *c, soma_info *out)
+{
+    if (!c || !out) return SOMA_EINVAL;
+    out->n_systems = (int32_t)c->sys.size();
+    out->n_tiles = c->L.n_tiles;
+    int64_t beads = 0, cells = 0;
+    for (const HostSys &h : c->sys) {
+        beads += (int64_t)h.d.n_chains * h.d.N;
+        cells += h.dev.n_cells;
+    }
+    out->n_beads = beads;
+    out->n_cells = cells;
+    out->sweep = c->sweep;
+    // positions read + write, counts read (gather), scatter and clear (per cell word)
+    const int64_t pos = c->repr == soma::REPR_F32 ? 12 : 24;
+    const int64_t cnt = c->cw == soma::COUNT_U16 ? 4 : 8;
+    out->bytes_per_sweep = 2 * pos * beads + 3 * cnt * cells;
+    out->density_mode = c->density_mode;
+    out->waves_per_block = c->waves_per_block;
+    return SOMA_OK;
+}
+
+const char *soma_last_error(const soma_ctx *c)
+{
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,801 @@
+// soma_kernels.hip -- HIP kernels of the SCMF Monte-Carlo sweep for gfx950.
+//
+// The method (Sec. 2, SOMA paragraph, and Sec. 2.2 of the paper): chains
+// move independently under frozen quasi-instantaneous fields; each sweep
+// performs biased/Metropolis trial moves with energy evaluations, then
+// rebuilds the particle density fields, then refreshes the fields.
+//
+// Mapping onto CDNA4
+//   * One wavefront owns a tile of whole chains: lane p of a chain holds the
+//     bead pair (2p, 2p+1), so a chain of N <= 128 beads fits one wave and
+//     the bond neighbours of a bead sit in the same lane or the adjacent
+//     lane (cross-lane exchange with ds_bpermute; no LDS, no barrier).
+//   * Positions are SoA with chains stored at an even stride, so each lane
+//     reads and writes one 8-byte pair per coordinate: fully coalesced.
+//   * The even pass moves bead 2p of every lane, the odd pass bead 2p+1;
+//     beads of one parity share no bond, so all lanes move at once.
+//   * The fields are never stored: omega of a cell is an affine function of
+//     its two counts, evaluated where a moved bead needs it (only when the
+//     trial move leaves the bead's cell).  The sweep kernel therefore does
+//     move + density + field in one launch: it reads the counts of sweep s,
+//     atomically scatters the counts of sweep s+1 into a zeroed buffer and
+//     clears the buffer of sweep s+2 (three count buffers in rotation).
+//   * Philox4x32-10 is counter based: one 128-bit block per (bead, logical
+//     chain, sweep, system); no RNG state lives in memory.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "soma_launch.hpp"
+#include "soma_types.hpp"
+
+namespace soma {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// multiplies with the key bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t nx = (uint32_t)(m1 >> 32) ^ c.y ^ k0;
+        const uint32_t nz = (uint32_t)(m0 >> 32) ^ c.w ^ k1;
+        c.y = (uint32_t)m1;
+        c.w = (uint32_t)m0;
+        c.x = nx;
+        c.z = nz;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+struct Draw {
+    float dx, dy, dz, u;
+};
+
+// Top 24 bits of each word: displacement = delta * ((w >> 8) - 2^23) * 2^-23
+// (one FP32 multiply of exact operands), acceptance variate u = (w >> 8) 2^-24.
+__device__ __forceinline__ Draw move_draw(uint32_t bead, uint32_t chain, uint32_t sweep,
+                                          uint32_t sys, uint32_t k0, uint32_t k1, float delta)
+{
+    const uint4 w = philox4x32_10(make_uint4(bead, chain, sweep, sys), k0, k1);
+    Draw d;
+    d.dx = delta * ((float)((int)(w.x >> 8) - 8388608) * 0x1p-23f);
+    d.dy = delta * ((float)((int)(w.y >> 8) - 8388608) * 0x1p-23f);
+    d.dz = delta * ((float)((int)(w.z >> 8) - 8388608) * 0x1p-23f);
+    d.u = (float)(w.w >> 8) * 0x1p-24f;
+    return d;
+}
+
+// Periodic wrap of an unwrapped cell index into [0, n); exact for |i| < 2^24.
+__device__ __forceinline__ int wrap_cell(int i, int n, float inv_n)
+{
+    const int q = (int)floorf((float)i * inv_n);
+    int r = i - q * n;
+    r = r < 0 ? r + n : r;
+    r = r >= n ? r - n : r;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Position representations
+// ---------------------------------------------------------------------------
+struct SysView {            // the per-system scalars a wave needs (SGPR resident)
+    int n0, n1, n2;
+    float inv_n0, inv_n1, inv_n2;
+    float e0, e1, e2;
+    float ie0, ie1, ie2;
+};
+
+struct BeadF32 {
+    float x, y, z;
+};
+struct BeadCell {
+    int cx, cy, cz;
+    float ox, oy, oz;
+};
+
+// Unwrapped cell indexes must stay where the float-reciprocal wrap is exact
+// (|i| < 2^24); beyond 2^23 the bead is flagged and counted in cell 0.
+constexpr int kCellLimit = 1 << 23;
+
+__device__ __forceinline__ float3 bond(const BeadF32 &a, const BeadF32 &b, const SysView &)
+{
+    return make_float3(a.x - b.x, a.y - b.y, a.z - b.z);
+}
+__device__ __forceinline__ float3 bond(const BeadCell &a, const BeadCell &b, const SysView &v)
+{
+    return make_float3((float)(a.cx - b.cx) * v.e0 + (a.ox - b.ox),
+                       (float)(a.cy - b.cy) * v.e1 + (a.oy - b.oy),
+                       (float)(a.cz - b.cz) * v.e2 + (a.oz - b.oz));
+}
+
+__device__ __forceinline__ BeadF32 propose(const BeadF32 &a, const Draw &d, const SysView &)
+{
+    return BeadF32{a.x + d.dx, a.y + d.dy, a.z + d.dz};
+}
+
+// Keep the offset in [0, edge) by whole-cell steps, each one FP32 rounding;
+// an offset that rounds up to exactly one edge moves to offset 0 of the next cell.
+__device__ __forceinline__ void renorm(int &c, float &o, float e)
+{
+    while (o < 0.0f) { o = o + e; c -= 1; }
+    while (o >= e) { o = o - e; c += 1; }
+}
+
+__device__ __forceinline__ BeadCell propose(const BeadCell &a, const Draw &d, const SysView &v)
+{
+    BeadCell n{a.cx, a.cy, a.cz, a.ox + d.dx, a.oy + d.dy, a.oz + d.dz};
+    renorm(n.cx, n.ox, v.e0);
+    renorm(n.cy, n.oy, v.e1);
+    renorm(n.cz, n.oz, v.e2);
+    return n;
+}
+
+// Linear NGP cell of a bead; sets `bad` when the unwrapped index leaves the
+// range the wrap handles (or the coordinate is not finite).
+__device__ __forceinline__ int cell_of(const BeadF32 &a, const SysView &v, bool &bad)
+{
+    const float fx = floorf(a.x * v.ie0), fy = floorf(a.y * v.ie1), fz = floorf(a.z * v.ie2);
+    const float lim = (float)kCellLimit;
+    if (!(fabsf(fx) < lim && fabsf(fy) < lim && fabsf(fz) < lim)) {
+        bad = true;
+        return 0;
+    }
+    const int ix = wrap_cell((int)fx, v.n0, v.inv_n0);
+    const int iy = wrap_cell((int)fy, v.n1, v.inv_n1);
+    const int iz = wrap_cell((int)fz, v.n2, v.inv_n2);
+    return (ix * v.n1 + iy) * v.n2 + iz;
+}
+__device__ __forceinline__ int cell_of(const BeadCell &a, const SysView &v, bool &bad)
+{
+    if (a.cx <= -kCellLimit || a.cx >= kCellLimit || a.cy <= -kCellLimit || a.cy >= kCellLimit ||
+        a.cz <= -kCellLimit || a.cz >= kCellLimit) {
+        bad = true;
+        return 0;
+    }
+    const int ix = wrap_cell(a.cx, v.n0, v.inv_n0);
+    const int iy = wrap_cell(a.cy, v.n1, v.inv_n1);
+    const int iz = wrap_cell(a.cz, v.n2, v.inv_n2);
+    return (ix * v.n1 + iy) * v.n2 + iz;
+}
+
+__device__ __forceinline__ BeadF32 shfl_up1(const BeadF32 &a)
+{
+    return BeadF32{__shfl_up(a.x, 1), __shfl_up(a.y, 1), __shfl_up(a.z, 1)};
+}
+__device__ __forceinline__ BeadF32 shfl_down1(const BeadF32 &a)
+{
+    return BeadF32{__shfl_down(a.x, 1), __shfl_down(a.y, 1), __shfl_down(a.z, 1)};
+}
+__device__ __forceinline__ BeadCell shfl_up1(const BeadCell &a)
+{
+    return BeadCell{__shfl_up(a.cx, 1), __shfl_up(a.cy, 1), __shfl_up(a.cz, 1),
+                    __shfl_up(a.ox, 1), __shfl_up(a.oy, 1), __shfl_up(a.oz, 1)};
+}
+__device__ __forceinline__ BeadCell shfl_down1(const BeadCell &a)
+{
+    return BeadCell{__shfl_down(a.cx, 1), __shfl_down(a.cy, 1), __shfl_down(a.cz, 1),
+                    __shfl_down(a.ox, 1), __shfl_down(a.oy, 1), __shfl_down(a.oz, 1)};
+}
+
+// Positions: F32 keeps coordinates in P0..P2; CELL keeps offsets in P0..P2
+// and cells in C0..C2.  `slot` is even, so pairs are 8-byte aligned.
+struct PosArrays {
+    float *P0, *P1, *P2;
+    int *C0, *C1, *C2;
+};
+
+__device__ __forceinline__ void load_pair(const PosArrays &A, int64_t slot, BeadF32 &a, BeadF32 &b)
+{
+    const float2 x = *reinterpret_cast<const float2 *>(A.P0 + slot);
+    const float2 y = *reinterpret_cast<const float2 *>(A.P1 + slot);
+    const float2 z = *reinterpret_cast<const float2 *>(A.P2 + slot);
+    a = BeadF32{x.x, y.x, z.x};
+    b = BeadF32{x.y, y.y, z.y};
+}
+__device__ __forceinline__ void store_pair(const PosArrays &A, int64_t slot, const BeadF32 &a,
+                                           const BeadF32 &b)
+{
+    *reinterpret_cast<float2 *>(A.P0 + slot) = make_float2(a.x, b.x);
+    *reinterpret_cast<float2 *>(A.P1 + slot) = make_float2(a.y, b.y);
+    *reinterpret_cast<float2 *>(A.P2 + slot) = make_float2(a.z, b.z);
+}
+__device__ __forceinline__ void load_pair(const PosArrays &A, int64_t slot, BeadCell &a, BeadCell &b)
+{
+    const int2 cx = *reinterpret_cast<const int2 *>(A.C0 + slot);
+    const int2 cy = *reinterpret_cast<const int2 *>(A.C1 + slot);
+    const int2 cz = *reinterpret_cast<const int2 *>(A.C2 + slot);
+    const float2 x = *reinterpret_cast<const float2 *>(A.P0 + slot);
+    const float2 y = *reinterpret_cast<const float2 *>(A.P1 + slot);
+    const float2 z = *reinterpret_cast<const float2 *>(A.P2 + slot);
+    a = BeadCell{cx.x, cy.x, cz.x, x.x, y.x, z.x};
+    b = BeadCell{cx.y, cy.y, cz.y, x.y, y.y, z.y};
+}
+__device__ __forceinline__ void store_pair(const PosArrays &A, int64_t slot, const BeadCell &a,
+                                           const BeadCell &b)
+{
+    *reinterpret_cast<int2 *>(A.C0 + slot) = make_int2(a.cx, b.cx);
+    *reinterpret_cast<int2 *>(A.C1 + slot) = make_int2(a.cy, b.cy);
+    *reinterpret_cast<int2 *>(A.C2 + slot) = make_int2(a.cz, b.cz);
+    *reinterpret_cast<float2 *>(A.P0 + slot) = make_float2(a.ox, b.ox);
+    *reinterpret_cast<float2 *>(A.P1 + slot) = make_float2(a.oy, b.oy);
+    *reinterpret_cast<float2 *>(A.P2 + slot) = make_float2(a.oz, b.oz);
+}
+
+// ---------------------------------------------------------------------------
+// Counts and fields
+// ---------------------------------------------------------------------------
+// U16: one uint32 per cell, A in the low half, B in the high half.
+// U32: two uint32 per cell (A, B) interleaved.
+template <int CW>
+__device__ __forceinline__ uint2 load_counts(const uint32_t *cnt, int64_t cell)
+{
+    if constexpr (CW == COUNT_U16) {
+        const uint32_t w = cnt[cell];
+        return make_uint2(w & 0xFFFFu, w >> 16);
+    } else {
+        return *reinterpret_cast<const uint2 *>(cnt + 2 * cell);
+    }
+}
+
+// Adds one bead of type t; returns true if the count overflowed its width.
+template <int CW>
+__device__ __forceinline__ bool scatter_count(uint32_t *cnt, int64_t cell, int t)
+{
+    if constexpr (CW == COUNT_U16) {
+        const uint32_t old = atomicAdd(cnt + cell, t ? 0x10000u : 1u);
+        return ((old >> (t ? 16 : 0)) & 0xFFFFu) == 0xFFFFu;
+    } else {
+        const uint32_t old = atomicAdd(cnt + 2 * cell + t, 1u);
+        return old == 0xFFFFFFFFu;
+    }
+}
+
+struct FieldCoef {
+    float aa, ab, ba, bb, c0;
+};
+
+// omega_t of a cell from its counts (affine in the counts).  The same
+// function produces the fields the sweep uses and the ones soma_fields reports.
+__device__ __forceinline__ float omega_of(const FieldCoef &f, uint2 n, int t)
+{
+    const float a = (float)n.x, b = (float)n.y;
+    return t ? fmaf(f.ba, a, fmaf(f.bb, b, f.c0)) : fmaf(f.aa, a, fmaf(f.ab, b, f.c0));
+}
+
+template <int CW>
+__device__ __forceinline__ float omega_at(bool frozen, const float2 *omega, const uint32_t *cnt,
+                                          int64_t cell_off, int cell, int t, const FieldCoef &f)
+{
+    if (frozen) {
+        const float2 w = omega[cell_off + cell];
+        return t ? w.y : w.x;
+    }
+    return omega_of(f, load_counts<CW>(cnt, cell_off + cell), t);
+}
+
+// Bead type from the system's 128-bit pattern.  All pattern words are loaded
+// as values and selected by value: a per-lane choice between word addresses
+// compiled (gfx950, -O3) into divergent branches that left the address of
+// the fourth word unset for beads 96..127.
+__device__ __forceinline__ int pattern_type(const DevSys &S, int chain, int i)
+{
+    const uint4 pa = *reinterpret_cast<const uint4 *>(S.pat_a);
+    const uint4 pb = *reinterpret_cast<const uint4 *>(S.pat_b);
+    const bool use_a = chain < S.n_chains_a;
+    const uint32_t x = use_a ? pa.x : pb.x, y = use_a ? pa.y : pb.y;
+    const uint32_t z = use_a ? pa.z : pb.z, w = use_a ? pa.w : pb.w;
+    const int k = i >> 5;
+    const uint32_t lo = (k & 1) ? y : x, hi = (k & 1) ? w : z;
+    const uint32_t word = (k & 2) ? hi : lo;
+    return (int)((word >> (i & 31)) & 1u);
+}
+
+__device__ __forceinline__ int wave_tile(int waves_per_block, int xcd_remap)
+{
+    int bid = (int)blockIdx.x;
+    if (xcd_remap) {
+        // Workgroups are dispatched round-robin over the 8 XCDs; give each
+        // XCD a contiguous range of tiles so its L2 sees a compact cell range.
+        const int nb = (int)gridDim.x;
+        const int full = nb & ~7;
+        if (bid < full) bid = (bid & 7) * (full >> 3) + (bid >> 3);
+    }
+    // wave-uniform by construction; readfirstlane lets the tile and system
+    // tables be read with scalar loads
+    return __builtin_amdgcn_readfirstlane(bid * waves_per_block + (int)(threadIdx.x >> 6));
+}
+
+__device__ __forceinline__ SysView make_view(const DevSys &S)
+{
+    SysView v;
+    v.n0 = S.n[0]; v.n1 = S.n[1]; v.n2 = S.n[2];
+    v.inv_n0 = S.inv_n[0]; v.inv_n1 = S.inv_n[1]; v.inv_n2 = S.inv_n[2];
+    v.e0 = S.edge[0]; v.e1 = S.edge[1]; v.e2 = S.edge[2];
+    v.ie0 = S.inv_edge[0]; v.ie1 = S.inv_edge[1]; v.ie2 = S.inv_edge[2];
+    return v;
+}
+
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// ---------------------------------------------------------------------------
+// The sweep kernel: even pass, odd pass, density scatter, clear of the
+// count buffer two sweeps ahead.  One launch per sweep for every system.
+// ---------------------------------------------------------------------------
+template <int R, int CW>
+__global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
+{
+    using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
+    const uint64_t s = *a.sweep_ctr + a.rel;
+    const uint32_t *cin = a.counts + (s % 3) * a.count_words;
+    uint32_t *cout = a.counts + ((s + 1) % 3) * a.count_words;
+    uint32_t *czero = a.counts + ((s + 2) % 3) * a.count_words;
+    {
+        const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.count_words; i += nthreads)
+            czero[i] = 0u;
+    }
+    const int wave = wave_tile(a.waves_per_block, a.xcd_remap);
+    if (wave >= a.n_tiles) return;
+    const Tile T = a.tiles[wave];
+    const DevSys &S = a.systems[T.sys];
+    const SysView v = make_view(S);
+    const FieldCoef fc{S.cAA, S.cAB, S.cBA, S.cBB, S.c0};
+    const bool frozen = S.frozen != 0;
+    const int N = S.N, P = S.P;
+    const int lane = (int)(threadIdx.x & 63);
+    const int g = lane / P;
+    const int p = lane - g * P;
+    const int nin = min(S.G, S.n_chains - (int)T.chain0);
+    const bool active = g < nin;
+    const int chain = (int)T.chain0 + (active ? g : 0);
+    const int i0 = 2 * p, i1 = 2 * p + 1;
+    const bool has1 = active && i1 < N;
+    const int64_t slot = S.slot_off + (int64_t)chain * (2 * P) + i0;
+    const PosArrays A{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2};
+
+    Bead b0{}, b1{};
+    if (active) load_pair(A, slot, b0, b1);
+    const uint32_t clog = a.chain_id ? a.chain_id[S.chain_off + chain] : (uint32_t)chain;
+    const int t0 = pattern_type(S, chain, i0);
+    const int t1 = pattern_type(S, chain, i1 < N ? i1 : i0);
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const Draw d0 = move_draw((uint32_t)i0, clog, (uint32_t)s, S.sys_id, k0, k1, S.delta);
+    const Draw d1 = move_draw((uint32_t)i1, clog, (uint32_t)s, S.sys_id, k0, k1, S.delta);
+    bool bad = false;
+    int cell0 = cell_of(b0, v, bad);
+    int cell1 = cell_of(b1, v, bad);
+    const float kh = S.k_half;
+
+    // even pass: bead 2p, neighbours 2p-1 (previous lane's odd bead) and 2p+1
+    bool acc0 = false;
+    {
+        const Bead left = shfl_up1(b1);
+        const Bead n0 = propose(b0, d0, v);
+        const float3 de = bond(n0, b0, v);
+        const float dd = dot3(de, de);
+        float dE = 0.0f;
+        if (p > 0) dE += 2.0f * dot3(de, bond(b0, left, v)) + dd;
+        if (i1 < N) dE += 2.0f * dot3(de, bond(b0, b1, v)) + dd;
+        dE *= kh;
+        const int nc = cell_of(n0, v, bad);
+        if (nc != cell0)
+            dE += omega_at<CW>(frozen, a.omega, cin, S.cell_off, nc, t0, fc) -
+                  omega_at<CW>(frozen, a.omega, cin, S.cell_off, cell0, t0, fc);
+        acc0 = active && (d0.u < expf(-dE));
+        if (acc0) {
+            b0 = n0;
+            cell0 = nc;
+        }
+    }
+    // odd pass: bead 2p+1, neighbours 2p (this lane, updated) and 2p+2 (next lane)
+    bool acc1 = false;
+    {
+        const Bead right = shfl_down1(b0);
+        const Bead n1 = propose(b1, d1, v);
+        const float3 de = bond(n1, b1, v);
+        const float dd = dot3(de, de);
+        float dE = 2.0f * dot3(de, bond(b1, b0, v)) + dd;
+        if (i1 + 1 < N) dE += 2.0f * dot3(de, bond(b1, right, v)) + dd;
+        dE *= kh;
+        const int nc = cell_of(n1, v, bad);
+        if (has1 && nc != cell1)
+            dE += omega_at<CW>(frozen, a.omega, cin, S.cell_off, nc, t1, fc) -
+                  omega_at<CW>(frozen, a.omega, cin, S.cell_off, cell1, t1, fc);
+        acc1 = has1 && (d1.u < expf(-dE));
+        if (acc1) {
+            b1 = n1;
+            cell1 = nc;
+        }
+    }
+    if (active) store_pair(A, slot, b0, b1);
+
+    bool ovf = false;
+    if (active) ovf |= scatter_count<CW>(cout, S.cell_off + cell0, t0);
+    if (has1) ovf |= scatter_count<CW>(cout, S.cell_off + cell1, t1);
+
+    const uint64_t nacc = __popcll(__ballot(acc0)) + __popcll(__ballot(acc1));
+    const bool any_ovf = __ballot(ovf) != 0;
+    const bool any_bad = __ballot(active && bad) != 0;
+    if (lane == 0) {
+        if (nacc) atomicAdd(a.accept + T.sys, (unsigned long long)nacc);
+        if (any_ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
+        if (any_bad) atomicOr(a.status, ST_CELL_OVERFLOW);
+    }
+}
+
+// Density of the current positions into a zeroed count buffer (creation,
+// soma_set_positions / soma_set_state).  Same tile mapping as the sweep.
+template <int R, int CW>
+__global__ __launch_bounds__(256) void k_density(DensityArgs a)
+{
+    using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
+    const int wave = __builtin_amdgcn_readfirstlane(
+        a.tile_begin + (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    if (wave >= a.tile_end) return;
+    const Tile T = a.tiles[wave];
+    const DevSys &S = a.systems[T.sys];
+    const SysView v = make_view(S);
+    const int N = S.N, P = S.P;
+    const int lane = (int)(threadIdx.x & 63);
+    const int g = lane / P;
+    const int p = lane - g * P;
+    const int nin = min(S.G, S.n_chains - (int)T.chain0);
+    const bool active = g < nin;
+    if (!active) return;
+    const int chain = (int)T.chain0 + g;
+    const int i0 = 2 * p, i1 = 2 * p + 1;
+    const int64_t slot = S.slot_off + (int64_t)chain * (2 * P) + i0;
+    const PosArrays A{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2};
+    Bead b0, b1;
+    load_pair(A, slot, b0, b1);
+    bool bad = false, ovf = false;
+    const int c0 = cell_of(b0, v, bad);
+    ovf |= scatter_count<CW>(a.counts, S.cell_off + c0, pattern_type(S, chain, i0));
+    if (i1 < N) {
+        const int c1 = cell_of(b1, v, bad);
+        ovf |= scatter_count<CW>(a.counts, S.cell_off + c1, pattern_type(S, chain, i1));
+    }
+    if (ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
+    if (bad) atomicOr(a.status, ST_CELL_OVERFLOW);
+}
+
+// Fields of one system as float [2][M] (A then B), from its counts or its
+// frozen array.
+template <int CW>
+__global__ __launch_bounds__(256) void k_fields(FieldArgs a)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_cells) return;
+    const DevSys &S = a.systems[a.sys];
+    float wa, wb;
+    if (S.frozen) {
+        const float2 w = a.omega[S.cell_off + c];
+        wa = w.x;
+        wb = w.y;
+    } else {
+        const FieldCoef fc{S.cAA, S.cAB, S.cBA, S.cBB, S.c0};
+        const uint2 n = load_counts<CW>(a.counts, S.cell_off + c);
+        wa = omega_of(fc, n, 0);
+        wb = omega_of(fc, n, 1);
+    }
+    a.out[c] = wa;
+    a.out[a.n_cells + c] = wb;
+}
+
+// Counts of one system as uint32 [2][M].
+template <int CW>
+__global__ __launch_bounds__(256) void k_unpack_counts(const uint32_t *counts, int64_t cell_off,
+                                                       int64_t n_cells, uint32_t *out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const uint2 n = load_counts<CW>(counts, cell_off + c);
+    out[c] = n.x;
+    out[n_cells + c] = n.y;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_advance(uint64_t *ctr, uint32_t n) { *ctr += n; }
+
+// ---------------------------------------------------------------------------
+// Initial configuration: Gaussian random walks on the GPU (Sec. 2.2 moved
+// the generation of bead coordinates to the GPU).  One thread per chain,
+// FP64 accumulation along the chain, then rounding to the representation.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void store_init(const InitArgs &a, int64_t slot, double x, double y,
+                                           double z)
+{
+    if (a.repr == REPR_F32) {
+        a.P0[slot] = (float)x;
+        a.P1[slot] = (float)y;
+        a.P2[slot] = (float)z;
+        return;
+    }
+    const double r[3] = {x, y, z};
+    float *P[3] = {a.P0, a.P1, a.P2};
+    int *C[3] = {a.C0, a.C1, a.C2};
+    for (int d = 0; d < 3; ++d) {
+        const float e = a.edge[d];
+        const double cf = floor(r[d] / (double)e);
+        int c = (int)cf;
+        float o = (float)(r[d] - cf * (double)e);
+        renorm(c, o, e);
+        C[d][slot] = c;
+        P[d][slot] = o;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_init_walks(InitArgs a)
+{
+    const int chain = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (chain >= a.n_chains) return;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const double two_pi = 6.283185307179586476925286766559;
+    double x = 0, y = 0, z = 0;
+    const int64_t base = a.slot_off + (int64_t)chain * a.stride;
+    for (int i = 0; i < a.N; ++i) {
+        const uint4 w = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)chain, 0u, a.sys_id | 0x80000000u),
+                                      k0, k1);
+        if (i == 0) {
+            x = a.box[0] * ((double)(w.x >> 8) * 0x1p-24);
+            y = a.box[1] * ((double)(w.y >> 8) * 0x1p-24);
+            z = a.box[2] * ((double)(w.z >> 8) * 0x1p-24);
+        } else {
+            const double u1 = ((double)(w.x >> 8) + 0.5) * 0x1p-24;
+            const double u2 = (double)(w.y >> 8) * 0x1p-24;
+            const double u3 = ((double)(w.z >> 8) + 0.5) * 0x1p-24;
+            const double u4 = (double)(w.w >> 8) * 0x1p-24;
+            const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
+            x += a.sigma * r1 * cos(two_pi * u2);
+            y += a.sigma * r1 * sin(two_pi * u2);
+            z += a.sigma * r2 * cos(two_pi * u4);
+        }
+        store_init(a, base + i, x, y, z);
+    }
+    for (int i = a.N; i < a.stride; ++i) store_init(a, base + i, 0.0, 0.0, 0.0);   // padding slot
+}
+
+// ---------------------------------------------------------------------------
+// Observables: FP64 per chain, compensated (Neumaier) block sums.  These are
+// the only FP64 operations on the GPU.
+// ---------------------------------------------------------------------------
+struct NSum {
+    double s, c;
+};
+__device__ __forceinline__ void nadd(NSum &a, double v)
+{
+    const double t = a.s + v;
+    a.c += fabs(a.s) >= fabs(v) ? (a.s - t) + v : (v - t) + a.s;
+    a.s = t;
+}
+__device__ __forceinline__ void nmerge(NSum &a, const NSum &b)
+{
+    nadd(a, b.s);
+    a.c += b.c;
+}
+
+constexpr int kObsQ = 6;   // Re2, Re2^2, Rg2, Rg2^2, Ebond, Enb
+
+__device__ __forceinline__ double pos_f64(const ObsArgs &a, int d, int64_t slot)
+{
+    const float *P = d == 0 ? a.P0 : d == 1 ? a.P1 : a.P2;
+    if (a.repr == REPR_F32) return (double)P[slot];
+    const int *C = d == 0 ? a.C0 : d == 1 ? a.C1 : a.C2;
+    return (double)C[slot] * (double)a.edge[d] + (double)P[slot];
+}
+
+// Block-level deterministic tree reduction of kObsQ Neumaier sums.
+__device__ void block_reduce_store(NSum (&q)[kObsQ], double *partials, int block)
+{
+    __shared__ double sh_s[kObsQ][256];
+    __shared__ double sh_c[kObsQ][256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < kObsQ; ++k) {
+        sh_s[k][t] = q[k].s;
+        sh_c[k][t] = q[k].c;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            for (int k = 0; k < kObsQ; ++k) {
+                NSum x{sh_s[k][t], sh_c[k][t]};
+                nmerge(x, NSum{sh_s[k][t + w], sh_c[k][t + w]});
+                sh_s[k][t] = x.s;
+                sh_c[k][t] = x.c;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int k = 0; k < kObsQ; ++k) {
+            partials[(int64_t)block * 2 * kObsQ + 2 * k] = sh_s[k][0];
+            partials[(int64_t)block * 2 * kObsQ + 2 * k + 1] = sh_c[k][0];
+        }
+}
+
+__global__ __launch_bounds__(256) void k_obs_chains(ObsArgs a)
+{
+    NSum q[kObsQ];
+    for (int k = 0; k < kObsQ; ++k) q[k] = NSum{0.0, 0.0};
+    const int chain = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (chain < a.n_chains) {
+        const int64_t base = a.slot_off + (int64_t)chain * a.stride;
+        const int N = a.N;
+        double cm[3] = {0, 0, 0}, e2e = 0, bond = 0;
+        for (int d = 0; d < 3; ++d) {
+            const double r0 = pos_f64(a, d, base), rl = pos_f64(a, d, base + N - 1);
+            e2e += (rl - r0) * (rl - r0);
+            double prev = r0;
+            cm[d] = r0;
+            for (int i = 1; i < N; ++i) {
+                const double r = pos_f64(a, d, base + i);
+                bond += (r - prev) * (r - prev);
+                cm[d] += r;
+                prev = r;
+            }
+            cm[d] /= (double)N;
+        }
+        double g = 0;
+        for (int d = 0; d < 3; ++d)
+            for (int i = 0; i < N; ++i) {
+                const double r = pos_f64(a, d, base + i) - cm[d];
+                g += r * r;
+            }
+        g /= (double)N;
+        bond *= a.k_half;
+        nadd(q[0], e2e);
+        nadd(q[1], e2e * e2e);
+        nadd(q[2], g);
+        nadd(q[3], g * g);
+        nadd(q[4], bond);
+    }
+    block_reduce_store(q, a.partials, blockIdx.x);
+}
+
+// f(phiA, phiB) per cell; sum over cells times (B / M) / N gives H_nb / kT.
+template <int CW>
+__global__ __launch_bounds__(256) void k_obs_cells(ObsArgs a)
+{
+    NSum q[kObsQ];
+    for (int k = 0; k < kObsQ; ++k) q[k] = NSum{0.0, 0.0};
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < a.n_cells) {
+        const uint2 n = load_counts<CW>(a.counts, a.cell_off + c);
+        const double pa = (double)n.x * a.phi_per_count, pb = (double)n.y * a.phi_per_count;
+        const double inc = pa + pb - 1.0;
+        double f;
+        if (a.ham_form == 1)
+            f = a.chiN * pa * pb + 0.5 * a.kappaN * inc * inc;
+        else
+            f = 0.5 * a.kappaN * inc * inc - 0.25 * a.chiN * (pa - pb) * (pa - pb);
+        nadd(q[5], f);
+    }
+    block_reduce_store(q, a.partials, a.block_base + blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_obs_finalize(const double *partials, int n_blocks, double *out)
+{
+    __shared__ double sh_s[256], sh_c[256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < kObsQ; ++k) {
+        NSum acc{0.0, 0.0};
+        for (int b = t; b < n_blocks; b += 256)
+            nmerge(acc, NSum{partials[(int64_t)b * 2 * kObsQ + 2 * k], partials[(int64_t)b * 2 * kObsQ + 2 * k + 1]});
+        sh_s[t] = acc.s;
+        sh_c[t] = acc.c;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (t < w) {
+                NSum x{sh_s[t], sh_c[t]};
+                nmerge(x, NSum{sh_s[t + w], sh_c[t + w]});
+                sh_s[t] = x.s;
+                sh_c[t] = x.c;
+            }
+            __syncthreads();
+        }
+        if (t == 0) out[k] = sh_s[0] + sh_c[0];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int R, int CW>
+static hipError_t launch_sweep_t(const SweepArgs &a, int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_sweep<R, CW>), dim3(blocks), dim3(64 * a.waves_per_block), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(int repr, int cw, const SweepArgs &a, hipStream_t st)
+{
+    const int blocks = (a.n_tiles + a.waves_per_block - 1) / a.waves_per_block;
+    if (repr == REPR_F32)
+        return cw == COUNT_U16 ? launch_sweep_t<REPR_F32, COUNT_U16>(a, blocks, st)
+                               : launch_sweep_t<REPR_F32, COUNT_U32>(a, blocks, st);
+    return cw == COUNT_U16 ? launch_sweep_t<REPR_CELL, COUNT_U16>(a, blocks, st)
+                           : launch_sweep_t<REPR_CELL, COUNT_U32>(a, blocks, st);
+}
+
+hipError_t launch_density(int repr, int cw, const DensityArgs &a, hipStream_t st)
+{
+    const int n = a.tile_end - a.tile_begin;
+    if (n <= 0) return hipSuccess;
+    const int blocks = (n + 3) / 4;
+    if (repr == REPR_F32) {
+        if (cw == COUNT_U16) hipLaunchKernelGGL((k_density<REPR_F32, COUNT_U16>), dim3(blocks), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_density<REPR_F32, COUNT_U32>), dim3(blocks), dim3(256), 0, st, a);
+    } else {
+        if (cw == COUNT_U16) hipLaunchKernelGGL((k_density<REPR_CELL, COUNT_U16>), dim3(blocks), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_density<REPR_CELL, COUNT_U32>), dim3(blocks), dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(int cw, const FieldArgs &a, hipStream_t st)
+{
+    const int blocks = (int)((a.n_cells + 255) / 256);
+    if (blocks == 0) return hipSuccess;
+    if (cw == COUNT_U16) hipLaunchKernelGGL((k_fields<COUNT_U16>), dim3(blocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_fields<COUNT_U32>), dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off, int64_t n_cells,
+                                uint32_t *out, hipStream_t st)
+{
+    const int blocks = (int)((n_cells + 255) / 256);
+    if (blocks == 0) return hipSuccess;
+    if (cw == COUNT_U16) hipLaunchKernelGGL((k_unpack_counts<COUNT_U16>), dim3(blocks), dim3(256), 0, st, counts, cell_off, n_cells, out);
+    else hipLaunchKernelGGL((k_unpack_counts<COUNT_U32>), dim3(blocks), dim3(256), 0, st, counts, cell_off, n_cells, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(uint64_t *ctr, uint32_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, st, ctr, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const InitArgs &a, hipStream_t st)
+{
+    const int blocks = (a.n_chains + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_walks, dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_observables(int cw, const ObsArgs &a, double *out, hipStream_t st)
+{
+    const int bc = (a.n_chains + 255) / 256;
+    const int bm = (int)((a.n_cells + 255) / 256);
+    ObsArgs b = a;
+    hipLaunchKernelGGL(k_obs_chains, dim3(bc), dim3(256), 0, st, b);
+    b.block_base = bc;
+    if (cw == COUNT_U16) hipLaunchKernelGGL((k_obs_cells<COUNT_U16>), dim3(bm), dim3(256), 0, st, b);
+    else hipLaunchKernelGGL((k_obs_cells<COUNT_U32>), dim3(bm), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(256), 0, st, a.partials, bc + bm, out);
+    return hipGetLastError();
+}
+
+}  // namespace soma

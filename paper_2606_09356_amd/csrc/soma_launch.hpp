@@ -1,0 +1,88 @@
+// soma_launch.hpp -- kernel argument blocks and launchers of libsoma_mi355x.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "soma_types.hpp"
+
+namespace soma {
+
+struct SweepArgs {
+    const DevSys *systems;
+    const Tile *tiles;
+    int n_tiles;
+    int waves_per_block;
+    int xcd_remap;
+    const uint32_t *chain_id;      // logical chain id per chain slot, or null for identity
+    float *P0, *P1, *P2;           // coordinates (F32) or offsets (CELL)
+    int *C0, *C1, *C2;             // cells (CELL only)
+    uint32_t *counts;              // three rotating count buffers
+    int64_t count_words;           // uint32 words per buffer
+    const float2 *omega;           // frozen fields, per cell (A, B)
+    const uint64_t *sweep_ctr;     // sweeps done before this graph / launch sequence
+    uint32_t rel;                  // sweep index relative to *sweep_ctr
+    uint64_t seed;
+    unsigned long long *accept;    // per system
+    uint32_t *status;
+};
+
+struct DensityArgs {
+    const DevSys *systems;
+    const Tile *tiles;
+    int tile_begin, tile_end;
+    float *P0, *P1, *P2;
+    int *C0, *C1, *C2;
+    uint32_t *counts;              // the target buffer (zeroed by the caller)
+    uint32_t *status;
+};
+
+struct FieldArgs {
+    const DevSys *systems;
+    int sys;
+    int64_t n_cells;
+    const uint32_t *counts;        // the current buffer
+    const float2 *omega;
+    float *out;                    // [2][n_cells]
+};
+
+struct InitArgs {
+    int repr;
+    int n_chains, N, stride;
+    int64_t slot_off;
+    uint32_t sys_id;
+    uint64_t seed;
+    double box[3];
+    float edge[3];
+    double sigma;                  // Re / sqrt(3 (N - 1))
+    float *P0, *P1, *P2;
+    int *C0, *C1, *C2;
+};
+
+struct ObsArgs {
+    int repr;
+    int n_chains, N, stride;
+    int64_t slot_off;
+    float edge[3];
+    double k_half;
+    const float *P0, *P1, *P2;
+    const int *C0, *C1, *C2;
+    const uint32_t *counts;        // the current buffer
+    int64_t cell_off, n_cells;
+    double phi_per_count;          // M / B
+    double chiN, kappaN;
+    int ham_form;
+    double *partials;
+    int block_base;
+};
+
+hipError_t launch_sweep(int repr, int cw, const SweepArgs &a, hipStream_t st);
+hipError_t launch_density(int repr, int cw, const DensityArgs &a, hipStream_t st);
+hipError_t launch_fields(int cw, const FieldArgs &a, hipStream_t st);
+hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off, int64_t n_cells,
+                                uint32_t *out, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_advance(uint64_t *ctr, uint32_t n, hipStream_t st);
+hipError_t launch_init(const InitArgs &a, hipStream_t st);
+hipError_t launch_observables(int cw, const ObsArgs &a, double *out, hipStream_t st);
+
+}  // namespace soma

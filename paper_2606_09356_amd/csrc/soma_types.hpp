@@ -1,0 +1,53 @@
+// soma_types.hpp -- device-side tables of the SCMF sweep library.
+//
+// Shared by the kernels and the host runtime of libsoma_mi355x only.
+#pragma once
+#include <stdint.h>
+
+namespace soma {
+
+constexpr int kWave = 64;              // CDNA wavefront width
+constexpr int kMaxN = 128;             // beads per chain handled by one wave (2 beads per lane)
+constexpr int kPatternWords = kMaxN / 32;
+
+enum Repr : int { REPR_F32 = 0, REPR_CELL = 1 };
+enum CountW : int { COUNT_U16 = 0, COUNT_U32 = 1 };
+
+enum StatusBits : uint32_t {
+    ST_COUNT_OVERFLOW = 1u,
+    ST_NONFINITE = 2u,
+    ST_CELL_OVERFLOW = 4u,
+};
+
+// One system, as the kernels see it.  Offsets are in elements of the flat
+// arrays shared by all systems of a context.
+struct alignas(16) DevSys {
+    int64_t slot_off;      // first bead slot (chains stored with an even stride 2P)
+    int64_t cell_off;      // first cell of the count / field arrays
+    int64_t chain_off;     // first chain of the context-wide chain arrays
+    int32_t n_chains;
+    int32_t N;             // beads per chain
+    int32_t P;             // bead pairs per chain = ceil(N/2); lane p holds beads 2p, 2p+1
+    int32_t G;             // chains per wave tile = 64 / P
+    int32_t n_chains_a;    // chains [0, n_chains_a) use pat_a
+    uint32_t sys_id;       // Philox counter word 3
+    int32_t n[3];          // grid
+    int32_t frozen;        // 1: fields come from the frozen array, else from the counts
+    float inv_n[3];        // 1 / n, for the periodic wrap
+    float edge[3];         // cell edge (FP32)
+    float inv_edge[3];     // 1 / edge (FP32)
+    float k_half;          // k/2 = 3(N-1)/(2 Re^2)
+    float delta;           // move half-width
+    // omega_A = cAA nA + cAB nB + c0, omega_B = cBA nA + cBB nB + c0
+    float cAA, cAB, cBA, cBB, c0;
+    int64_t n_cells;
+    alignas(16) uint32_t pat_a[kPatternWords];   // bit i: type of bead i (0 = A, 1 = B)
+    alignas(16) uint32_t pat_b[kPatternWords];
+};
+
+struct Tile {
+    uint32_t sys;          // index into the system table (not the Philox system id)
+    uint32_t chain0;       // first chain of the tile within its system
+};
+
+}  // namespace soma

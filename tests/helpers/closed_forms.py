@@ -1,0 +1,61 @@
+"""Closed forms of the model used as pins (independent of oracle and GPU code).
+
+acceptance_closed_form: chain-mean Metropolis acceptance of ideal chains at
+  equilibrium.  For a trial displacement d, dE is Gaussian with mean mu and
+  variance 2 mu (mu = k|d|^2 interior, k|d|^2/2 end bead), so
+  P(accept | d) = 2 Phi(-sqrt(mu/2)); the mean over the uniform cube is a
+  Gauss-Legendre quadrature.
+pair_weight_1d: sum over periodic images of the double integral of the bond
+  weight exp(-(k/2)(x-y)^2) over two grid cells, by the erf antiderivative.
+two_bead_cell_probabilities: exact joint cell occupancy of a two-bead chain
+  (A-B) with harmonic bond k in frozen fields omega_A, omega_B.
+"""
+import math
+
+import numpy as np
+from scipy import special
+
+
+def acceptance_closed_form(N, delta, Re=1.0, n_nodes=64):
+    k = 3.0 * (N - 1) / Re ** 2
+    x, w = np.polynomial.legendre.leggauss(n_nodes)
+    x = 0.5 * delta * (x + 1.0)
+    w = 0.5 * w
+    d2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+    ww = w[:, None, None] * w[None, :, None] * w[None, None, :]
+
+    def mean_acc(mu):
+        return float((ww * 2.0 * special.ndtr(-np.sqrt(mu / 2.0))).sum())
+    if N == 1:
+        return 1.0
+    p_int = mean_acc(k * d2)
+    p_end = mean_acc(0.5 * k * d2)
+    return (2 * p_end + (N - 2) * p_int) / N
+
+
+def pair_weight_1d(n, L, k, n_images=6):
+    a = 0.5 * k
+    F = lambda u: 0.5 * math.sqrt(math.pi / a) * special.erf(math.sqrt(a) * u)
+    G2 = lambda u: u * F(u) + (math.exp(-a * u * u) - 1.0) / (2 * a)
+    h = L / n
+    Wm = np.zeros((n, n))
+    for i in range(n):
+        lo1, hi1 = i * h, (i + 1) * h
+        for j in range(n):
+            tot = 0.0
+            for m in range(-n_images, n_images + 1):
+                lo2, hi2 = j * h + m * L, (j + 1) * h + m * L
+                tot += G2(hi1 - lo2) - G2(hi1 - hi2) - G2(lo1 - lo2) + G2(lo1 - hi2)
+            Wm[i, j] = tot
+    return Wm
+
+
+def two_bead_cell_probabilities(omega, n, L, k):
+    """P[c1, c2] for cubic grid n^3, linear index (ix*n + iy)*n + iz."""
+    M = n ** 3
+    Wx = pair_weight_1d(n, L, k)
+    idx = np.array(np.unravel_index(np.arange(M), (n, n, n)))
+    Wpair = Wx[idx[0][:, None], idx[0][None, :]] * Wx[idx[1][:, None], idx[1][None, :]] \
+        * Wx[idx[2][:, None], idx[2][None, :]]
+    P = np.exp(-omega[0])[:, None] * np.exp(-omega[1])[None, :] * Wpair
+    return P / P.sum(), idx

@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports every function include/soma.h declares;
+host-side argument checks (no GPU work) return the documented codes."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2606_09356_amd import soma as S
+from paper_2606_09356_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "soma.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(soma_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(S.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return S.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = header_functions()
+    assert len(names) >= 17, names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(S.EXPORTS) == set(names)
+
+
+def _opts(**kw):
+    o = S.soma_options()
+    o.seed, o.pos_repr, o.count_width, o.use_graph = 1, S.POS_F32, S.COUNT_U16, 1
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_workspace_size_scales_with_representation(lib):
+    sysd = W.plain_small()
+    arr, keep = S._desc_array(sysd)
+    sizes = {}
+    for repr_, cw in [(S.POS_F32, S.COUNT_U16), (S.POS_CELL_F32, S.COUNT_U32)]:
+        n = C.c_size_t(0)
+        assert lib.soma_workspace_size(arr, 1, C.byref(_opts(pos_repr=repr_, count_width=cw)), C.byref(n)) == 0
+        sizes[(repr_, cw)] = n.value
+    B, M = sysd[0].n_beads, sysd[0].n_cells
+    assert sizes[(S.POS_F32, S.COUNT_U16)] >= 12 * B + 3 * 4 * M + 8 * M
+    assert sizes[(S.POS_CELL_F32, S.COUNT_U32)] - sizes[(S.POS_F32, S.COUNT_U16)] >= 12 * B + 3 * 4 * M
+
+
+@pytest.mark.parametrize("field,value", [("N", 1), ("N", 129), ("n_chains", 0), ("n_chains_a", 300),
+                                         ("move_halfwidth", 0.3), ("chiN", float("nan")),
+                                         ("ham_form", 2), ("grid", (0, 16, 16))])
+def test_invalid_descriptors_are_rejected(lib, field, value):
+    s = W.plain_small()[0]
+    arr, keep = S._desc_array([s])
+    if field == "grid":
+        arr[0].grid = (C.c_int32 * 3)(*value)
+    else:
+        setattr(arr[0], field, value)
+    n = C.c_size_t(0)
+    assert lib.soma_workspace_size(arr, 1, C.byref(_opts()), C.byref(n)) == S.SOMA_EINVAL
+    assert lib.soma_last_error(None)
+
+
+def test_invalid_options_are_rejected(lib):
+    arr, keep = S._desc_array(W.plain_small())
+    n = C.c_size_t(0)
+    for kw in [dict(pos_repr=3), dict(count_width=7), dict(waves_per_block=17), dict(density_mode=2),
+               dict(sys_id_base=-1)]:
+        assert lib.soma_workspace_size(arr, 1, C.byref(_opts(**kw)), C.byref(n)) == S.SOMA_EINVAL, kw
+
+
+def test_create_rejects_short_or_misaligned_workspace(lib):
+    arr, keep = S._desc_array(W.plain_small())
+    ctx = C.c_void_p()
+    buf = (C.c_uint8 * 4096)()
+    # misaligned pointer: rejected before any device call
+    addr = C.addressof(buf)
+    mis = addr + (1 if addr % 256 == 0 else 0)
+    assert lib.soma_create(arr, 1, C.byref(_opts()), mis, 4096, C.byref(ctx)) == S.SOMA_EINVAL
+    aligned = (addr + 255) & ~255
+    assert lib.soma_create(arr, 1, C.byref(_opts()), aligned, 1024, C.byref(ctx)) == S.SOMA_ENOMEM
+    assert not ctx.value

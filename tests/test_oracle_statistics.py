@@ -24,6 +24,8 @@ import pytest
 from scipy import integrate, special, stats
 
 from paper_2606_09356_amd import workloads as W
+from tests.helpers.closed_forms import (acceptance_closed_form, pair_weight_1d,
+                                        two_bead_cell_probabilities)
 
 
 def ideal_system(n_chains, N, box=16.0, delta=0.05):
@@ -31,24 +33,6 @@ def ideal_system(n_chains, N, box=16.0, delta=0.05):
     s = W.diblock_system(n_chains, N, 0.5, 0.0, 0.0, (box, box, box), (g, g, g))
     s.move_halfwidth = delta
     return s
-
-
-def acceptance_closed_form(N, delta, Re=1.0, n_nodes=64):
-    """Chain-mean acceptance ratio of ideal chains at equilibrium."""
-    k = 3.0 * (N - 1) / Re ** 2
-    x, w = np.polynomial.legendre.leggauss(n_nodes)
-    x = 0.5 * delta * (x + 1.0)          # nodes on [0, delta] (the integrand is even)
-    w = 0.5 * w                          # weights for the mean over [0, delta]
-    d2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
-    ww = w[:, None, None] * w[None, :, None] * w[None, None, :]
-
-    def mean_acc(mu):
-        return float((ww * 2.0 * special.ndtr(-np.sqrt(mu / 2.0))).sum())
-    if N == 1:
-        return 1.0
-    p_int = mean_acc(k * d2)
-    p_end = mean_acc(0.5 * k * d2)
-    return (2 * p_end + (N - 2) * p_int) / N
 
 
 def test_closed_form_sanity():
@@ -128,27 +112,9 @@ def test_two_bead_bond_length_is_maxwell(orc):
     assert b.mean() == pytest.approx(stats.maxwell(scale=1 / math.sqrt(3.0)).mean(), rel=0.005)
 
 
-def _pair_weight_1d(n, L, k, n_images=6):
-    """W[i, j] = sum_m int_{I_i} int_{I_j + m L} exp(-(k/2)(x - y)^2) dy dx."""
-    a = 0.5 * k
-    F = lambda u: 0.5 * math.sqrt(math.pi / a) * special.erf(math.sqrt(a) * u)
-    G2 = lambda u: u * F(u) + (math.exp(-a * u * u) - 1.0) / (2 * a)
-    h = L / n
-    Wm = np.zeros((n, n))
-    for i in range(n):
-        lo1, hi1 = i * h, (i + 1) * h
-        for j in range(n):
-            tot = 0.0
-            for m in range(-n_images, n_images + 1):
-                lo2, hi2 = j * h + m * L, (j + 1) * h + m * L
-                tot += G2(hi1 - lo2) - G2(hi1 - hi2) - G2(lo1 - lo2) + G2(lo1 - hi2)
-            Wm[i, j] = tot
-    return Wm
-
-
 def test_pair_weight_formula_against_quadrature():
     k, L, n = 3.0, 1.0, 4
-    Wm = _pair_weight_1d(n, L, k)
+    Wm = pair_weight_1d(n, L, k)
     h = L / n
     for (i, j) in [(0, 0), (0, 1), (1, 3), (2, 0)]:
         q = sum(integrate.dblquad(lambda y, x: math.exp(-0.5 * k * (x - y) ** 2),
@@ -179,13 +145,7 @@ def test_two_bead_frozen_field_boltzmann(orc):
         ix = np.floor(r[0] / (L / n)).astype(np.int64) % n
         np.add.at(joint_x, (ix[0::2], ix[1::2]), 1)
     # brute force
-    k_spring = 3.0
-    Wx = _pair_weight_1d(n, L, k_spring)
-    idx = np.array(np.unravel_index(np.arange(M), (n, n, n)))     # (3, M): ix, iy, iz
-    Wpair = Wx[idx[0][:, None], idx[0][None, :]] * Wx[idx[1][:, None], idx[1][None, :]] \
-        * Wx[idx[2][:, None], idx[2][None, :]]
-    P = np.exp(-omega[0])[:, None] * np.exp(-omega[1])[None, :] * Wpair
-    P /= P.sum()
+    P, idx = two_bead_cell_probabilities(omega, n, L, 3.0)
     pA_exp, pB_exp = P.sum(axis=1), P.sum(axis=0)
     pA_obs = acc_counts[0] / acc_counts[0].sum()
     pB_obs = acc_counts[1] / acc_counts[1].sum()
