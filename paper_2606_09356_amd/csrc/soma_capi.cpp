@@ -25,7 +25,7 @@ namespace {
 thread_local std::string g_create_error;
 
 struct Layout {
-    size_t systems, tiles, chain_id, P[3], C[3], counts, omega, accept, status, partials, obs_out,
+    size_t systems, tiles, chain_id, P[3], C[3], base, delta, omega, accept, status, partials, obs_out,
         staging, total;
     int64_t total_slots = 0, total_cells = 0, total_chains = 0, count_words = 0;
     int n_tiles = 0;
@@ -63,8 +63,11 @@ struct soma_ctx {
     Tile *d_tiles() const { return reinterpret_cast<Tile *>(ws + L.tiles); }
     float *P(int d) const { return reinterpret_cast<float *>(ws + L.P[d]); }
     int *C(int d) const { return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + L.C[d]) : nullptr; }
-    uint32_t *counts() const { return reinterpret_cast<uint32_t *>(ws + L.counts); }
-    uint32_t *counts_buf(uint64_t s) const { return counts() + (s % 3) * L.count_words; }
+    // Counts after S sweeps are base[(S-1) mod 2] + delta[(S-1) mod 3].
+    uint32_t *base() const { return reinterpret_cast<uint32_t *>(ws + L.base); }
+    uint32_t *delta() const { return reinterpret_cast<uint32_t *>(ws + L.delta); }
+    uint32_t *cur_base(uint64_t S) const { return base() + ((S + 1) % 2) * L.count_words; }
+    uint32_t *cur_delta(uint64_t S) const { return delta() + ((S + 2) % 3) * L.count_words; }
     float2 *omega() const { return reinterpret_cast<float2 *>(ws + L.omega); }
     unsigned long long *accept() const { return reinterpret_cast<unsigned long long *>(ws + L.accept); }
     uint32_t *status() const { return reinterpret_cast<uint32_t *>(ws + L.status); }
@@ -222,9 +225,10 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     L.chain_id = take(sizeof(uint32_t) * chains);
     for (int a = 0; a < 3; ++a) L.P[a] = take(sizeof(float) * slots);
     for (int a = 0; a < 3; ++a) L.C[a] = cell ? take(sizeof(int) * slots) : 0;
-    L.counts = take(sizeof(uint32_t) * 3 * L.count_words);
+    L.base = take(sizeof(uint32_t) * 2 * L.count_words);
+    L.delta = take(sizeof(uint32_t) * 3 * L.count_words);
     L.omega = take(sizeof(float) * 2 * cells);
-    L.accept = take(sizeof(uint64_t) * n_sys);
+    L.accept = take(sizeof(uint64_t) * soma::kAcceptSlots * soma::kAcceptStride * n_sys);
     L.status = take(64);
     L.partials = take(sizeof(double) * 12 * max_blocks);
     L.obs_out = take(sizeof(double) * 8);
@@ -271,7 +275,8 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
         (&a.P0)[d] = c->P(d);
         (&a.C0)[d] = c->C(d);
     }
-    a.counts = c->counts();
+    a.base = c->base();
+    a.delta = c->delta();
     a.count_words = c->L.count_words;
     a.omega = c->omega();
     a.sweep_ctr = c->sweep_ctr();
@@ -282,17 +287,21 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
     return a;
 }
 
-// Rebuild the density of one system (or all when sys < 0) into the current buffer.
+// Rebuild the density of one system (or all when sys < 0) as the current
+// base counts with a zero delta.
 int rebuild_density(soma_ctx *c, int32_t sys)
 {
-    uint32_t *cur = c->counts_buf(c->sweep);
+    uint32_t *cur = c->cur_base(c->sweep);
+    uint32_t *dcur = c->cur_delta(c->sweep);
     const int64_t wpc = c->words_per_cell();
     int tb = 0, te = c->L.n_tiles;
     if (sys < 0) {
         HIPCHK(c, soma::launch_fill_u32(cur, c->L.count_words, 0u, c->stream));
+        HIPCHK(c, soma::launch_fill_u32(dcur, c->L.count_words, 0u, c->stream));
     } else {
         const HostSys &h = c->sys[sys];
         HIPCHK(c, soma::launch_fill_u32(cur + h.dev.cell_off * wpc, h.dev.n_cells * wpc, 0u, c->stream));
+        HIPCHK(c, soma::launch_fill_u32(dcur + h.dev.cell_off * wpc, h.dev.n_cells * wpc, 0u, c->stream));
         tb = h.tile_begin;
         te = h.tile_end;
     }
@@ -458,9 +467,11 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
         return bail(hip_fail(c, e, "upload tiles"));
     // clear counts, fields, accept counters, status and sweep counter
     if ((rc = [&] {
-             HIPCHK(c, soma::launch_fill_u32(c->counts(), 3 * c->L.count_words, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(c->base(), 2 * c->L.count_words, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(c->delta(), 3 * c->L.count_words, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->omega()), 2 * c->L.total_cells, 0u, c->stream));
-             HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->accept()), 2 * (int64_t)n_sys, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->accept()),
+                                             2 * (int64_t)soma::kAcceptSlots * soma::kAcceptStride * n_sys, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(c->status(), 16, 0u, c->stream));
              return (int)SOMA_OK;
          }()) != SOMA_OK)
@@ -537,7 +548,8 @@ int soma_density(soma_ctx *c, int32_t sys, uint32_t *dst, int32_t dst_on_device)
     if (!dst) return fail(c, SOMA_EINVAL, "dst is null");
     const HostSys &h = c->sys[sys];
     uint32_t *target = dst_on_device ? dst : static_cast<uint32_t *>(c->staging());
-    HIPCHK(c, soma::launch_unpack_counts(c->cw, c->counts_buf(c->sweep), h.dev.cell_off, h.dev.n_cells, target, c->stream));
+    HIPCHK(c, soma::launch_unpack_counts(c->cw, c->cur_base(c->sweep), c->cur_delta(c->sweep), h.dev.cell_off,
+                                         h.dev.n_cells, target, c->stream));
     if (!dst_on_device)
         HIPCHK(c, hipMemcpyAsync(dst, target, sizeof(uint32_t) * 2 * h.dev.n_cells, hipMemcpyDeviceToHost, c->stream));
     return sync_status(c);
@@ -554,7 +566,8 @@ int soma_fields(soma_ctx *c, int32_t sys, float *dst, int32_t dst_on_device)
     f.systems = c->d_sys();
     f.sys = sys;
     f.n_cells = h.dev.n_cells;
-    f.counts = c->counts_buf(c->sweep);
+    f.base = c->cur_base(c->sweep);
+    f.delta = c->cur_delta(c->sweep);
     f.omega = c->omega();
     f.out = dst_on_device ? dst : static_cast<float *>(c->staging());
     HIPCHK(c, soma::launch_fields(c->cw, f, c->stream));
@@ -582,7 +595,8 @@ int soma_observables(soma_ctx *c, int32_t sys, soma_obs *out)
         (&a.C0)[d] = c->C(d);
     }
     a.k_half = 1.5 * (h.d.N - 1) / (h.d.Re * h.d.Re);
-    a.counts = c->counts_buf(c->sweep);
+    a.base = c->cur_base(c->sweep);
+    a.delta = c->cur_delta(c->sweep);
     a.cell_off = h.dev.cell_off;
     a.n_cells = h.dev.n_cells;
     const double B = (double)h.d.n_chains * h.d.N;
@@ -594,10 +608,13 @@ int soma_observables(soma_ctx *c, int32_t sys, soma_obs *out)
     a.block_base = 0;
     HIPCHK(c, soma::launch_observables(c->cw, a, c->obs_out(), c->stream));
     double q[6];
-    unsigned long long acc = 0;
+    std::vector<unsigned long long> slots((size_t)soma::kAcceptSlots * soma::kAcceptStride);
     HIPCHK(c, hipMemcpyAsync(q, c->obs_out(), sizeof q, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&acc, c->accept() + sys, sizeof acc, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(slots.data(), c->accept() + (size_t)sys * slots.size(),
+                             sizeof(unsigned long long) * slots.size(), hipMemcpyDeviceToHost, c->stream));
     if ((rc = sync_status(c)) != SOMA_OK) return rc;
+    unsigned long long acc = 0;
+    for (int k = 0; k < soma::kAcceptSlots; ++k) acc += slots[(size_t)k * soma::kAcceptStride];
     const double n = (double)h.d.n_chains;
     out->Re2 = q[0] / n;
     out->Re2_err = std::sqrt(std::max(q[1] / n - out->Re2 * out->Re2, 0.0) / n);
@@ -748,7 +765,8 @@ int soma_set_sweep(soma_ctx *c, uint64_t sweep)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->sweep_ctr(), &sweep, sizeof sweep, hipMemcpyHostToDevice));
     c->sweep = sweep;
-    HIPCHK(c, soma::launch_fill_u32(c->counts(), 3 * c->L.count_words, 0u, c->stream));
+    HIPCHK(c, soma::launch_fill_u32(c->base(), 2 * c->L.count_words, 0u, c->stream));
+    HIPCHK(c, soma::launch_fill_u32(c->delta(), 3 * c->L.count_words, 0u, c->stream));
     if ((rc = rebuild_density(c, -1)) != SOMA_OK) return rc;
     return sync_status(c);
 }
@@ -766,10 +784,11 @@ int soma_get_info(soma_ctx *c, soma_info *out)
     out->n_beads = beads;
     out->n_cells = cells;
     out->sweep = c->sweep;
-    // positions read + write, counts read (gather), scatter and clear (per cell word)
+    // positions read + write; fold of the counts: base and delta read, base
+    // written, next delta cleared (the field gathers hit these same lines)
     const int64_t pos = c->repr == soma::REPR_F32 ? 12 : 24;
     const int64_t cnt = c->cw == soma::COUNT_U16 ? 4 : 8;
-    out->bytes_per_sweep = 2 * pos * beads + 3 * cnt * cells;
+    out->bytes_per_sweep = 2 * pos * beads + 4 * cnt * cells;
     out->density_mode = c->density_mode;
     out->waves_per_block = c->waves_per_block;
     return SOMA_OK;

@@ -16,10 +16,14 @@
 //     beads of one parity share no bond, so all lanes move at once.
 //   * The fields are never stored: omega of a cell is an affine function of
 //     its two counts, evaluated where a moved bead needs it (only when the
-//     trial move leaves the bead's cell).  The sweep kernel therefore does
-//     move + density + field in one launch: it reads the counts of sweep s,
-//     atomically scatters the counts of sweep s+1 into a zeroed buffer and
-//     clears the buffer of sweep s+2 (three count buffers in rotation).
+//     trial move leaves the bead's cell).
+//   * The density is kept as base counts plus a delta: a sweep adds -1/+1
+//     atomically only for accepted moves that change cell (about 0.2 of the
+//     beads), not one atomic per bead.  The counts of sweep s are
+//     B[s-1] + D[s-1]; sweep s reads them (fields), atomically accumulates
+//     its own changes in D[s], writes B[s] = B[s-1] + D[s-1] and clears
+//     D[s+1] -- two base and three delta buffers in rotation, so move,
+//     density and field refresh are one launch per sweep.
 //   * Philox4x32-10 is counter based: one 128-bit block per (bead, logical
 //     chain, sweep, system); no RNG state lives in memory.
 #include <hip/hip_runtime.h>
@@ -231,14 +235,54 @@ __device__ __forceinline__ void store_pair(const PosArrays &A, int64_t slot, con
 // ---------------------------------------------------------------------------
 // U16: one uint32 per cell, A in the low half, B in the high half.
 // U32: two uint32 per cell (A, B) interleaved.
+// Counts are base + delta in modular uint32 arithmetic: for U16 the packed
+// sum equals nA + 2^16 nB exactly whenever both true counts fit 16 bits.
+struct CountView {
+    const uint32_t *base;
+    const uint32_t *delta;
+};
+
 template <int CW>
-__device__ __forceinline__ uint2 load_counts(const uint32_t *cnt, int64_t cell)
+__device__ __forceinline__ uint2 load_counts(const CountView &v, int64_t cell)
 {
     if constexpr (CW == COUNT_U16) {
-        const uint32_t w = cnt[cell];
+        const uint32_t w = v.base[cell] + v.delta[cell];
         return make_uint2(w & 0xFFFFu, w >> 16);
     } else {
-        return *reinterpret_cast<const uint2 *>(cnt + 2 * cell);
+        const uint2 b = *reinterpret_cast<const uint2 *>(v.base + 2 * cell);
+        const uint2 d = *reinterpret_cast<const uint2 *>(v.delta + 2 * cell);
+        return make_uint2(b.x + d.x, b.y + d.y);
+    }
+}
+
+// One bead of type t leaves cell `from` and enters cell `to` (non-returning
+// atomics; the count ranges are checked when the delta is folded).
+template <int CW>
+__device__ __forceinline__ void move_count(uint32_t *delta, int64_t from, int64_t to, int t)
+{
+    if constexpr (CW == COUNT_U16) {
+        const uint32_t inc = t ? 0x10000u : 1u;
+        __hip_atomic_fetch_add(delta + from, 0u - inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(delta + to, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_fetch_add(delta + 2 * from + t, 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(delta + 2 * to + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Fold one word: base' = base + delta; returns true if a true count left its
+// range (below zero, or above 65535 for packed 16-bit counts).
+template <int CW>
+__device__ __forceinline__ bool fold_word(uint32_t b, uint32_t d, uint32_t &out)
+{
+    out = b + d;
+    if constexpr (CW == COUNT_U16) {
+        const int dA = (int)(int16_t)(d & 0xFFFFu);
+        const int dB = (int)(int16_t)((d - (uint32_t)dA) >> 16);
+        const int nA = (int)(b & 0xFFFFu) + dA, nB = (int)(b >> 16) + dB;
+        return nA < 0 || nA > 0xFFFF || nB < 0 || nB > 0xFFFF;
+    } else {
+        return (int)d >= 0 ? out < b : out > b;
     }
 }
 
@@ -268,7 +312,7 @@ __device__ __forceinline__ float omega_of(const FieldCoef &f, uint2 n, int t)
 }
 
 template <int CW>
-__device__ __forceinline__ float omega_at(bool frozen, const float2 *omega, const uint32_t *cnt,
+__device__ __forceinline__ float omega_at(bool frozen, const float2 *omega, const CountView &cnt,
                                           int64_t cell_off, int cell, int t, const FieldCoef &f)
 {
     if (frozen) {
@@ -331,14 +375,22 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
     const uint64_t s = *a.sweep_ctr + a.rel;
-    const uint32_t *cin = a.counts + (s % 3) * a.count_words;
-    uint32_t *cout = a.counts + ((s + 1) % 3) * a.count_words;
-    uint32_t *czero = a.counts + ((s + 2) % 3) * a.count_words;
+    const int64_t W = a.count_words;
+    const CountView cin{a.base + ((s + 1) & 1) * W, a.delta + ((s + 2) % 3) * W};   // counts of sweep s
+    uint32_t *bcur = a.base + (s & 1) * W;
+    uint32_t *dcur = a.delta + (s % 3) * W;
+    uint32_t *dnext = a.delta + ((s + 1) % 3) * W;
+    bool fold_ovf = false;
     {
         const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.count_words; i += nthreads)
-            czero[i] = 0u;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < W; i += nthreads) {
+            uint32_t w;
+            fold_ovf |= fold_word<CW>(cin.base[i], cin.delta[i], w);
+            bcur[i] = w;
+            dnext[i] = 0u;
+        }
     }
+    if (fold_ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
     const int wave = wave_tile(a.waves_per_block, a.xcd_remap);
     if (wave >= a.n_tiles) return;
     const Tile T = a.tiles[wave];
@@ -369,6 +421,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     bool bad = false;
     int cell0 = cell_of(b0, v, bad);
     int cell1 = cell_of(b1, v, bad);
+    const int old0 = cell0, old1 = cell1;
     const float kh = S.k_half;
 
     // even pass: bead 2p, neighbours 2p-1 (previous lane's odd bead) and 2p+1
@@ -414,16 +467,16 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     }
     if (active) store_pair(A, slot, b0, b1);
 
-    bool ovf = false;
-    if (active) ovf |= scatter_count<CW>(cout, S.cell_off + cell0, t0);
-    if (has1) ovf |= scatter_count<CW>(cout, S.cell_off + cell1, t1);
+    // density delta: only beads that changed cell
+    if (acc0 && cell0 != old0) move_count<CW>(dcur, S.cell_off + old0, S.cell_off + cell0, t0);
+    if (acc1 && cell1 != old1) move_count<CW>(dcur, S.cell_off + old1, S.cell_off + cell1, t1);
 
     const uint64_t nacc = __popcll(__ballot(acc0)) + __popcll(__ballot(acc1));
-    const bool any_ovf = __ballot(ovf) != 0;
     const bool any_bad = __ballot(active && bad) != 0;
     if (lane == 0) {
-        if (nacc) atomicAdd(a.accept + T.sys, (unsigned long long)nacc);
-        if (any_ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
+        if (nacc)
+            atomicAdd(a.accept + ((int64_t)T.sys * kAcceptSlots + (wave % kAcceptSlots)) * kAcceptStride,
+                      (unsigned long long)nacc);
         if (any_bad) atomicOr(a.status, ST_CELL_OVERFLOW);
     }
 }
@@ -479,7 +532,7 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs a)
         wb = w.y;
     } else {
         const FieldCoef fc{S.cAA, S.cAB, S.cBA, S.cBB, S.c0};
-        const uint2 n = load_counts<CW>(a.counts, S.cell_off + c);
+        const uint2 n = load_counts<CW>(CountView{a.base, a.delta}, S.cell_off + c);
         wa = omega_of(fc, n, 0);
         wb = omega_of(fc, n, 1);
     }
@@ -489,12 +542,12 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs a)
 
 // Counts of one system as uint32 [2][M].
 template <int CW>
-__global__ __launch_bounds__(256) void k_unpack_counts(const uint32_t *counts, int64_t cell_off,
-                                                       int64_t n_cells, uint32_t *out)
+__global__ __launch_bounds__(256) void k_unpack_counts(const uint32_t *base, const uint32_t *delta,
+                                                       int64_t cell_off, int64_t n_cells, uint32_t *out)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
-    const uint2 n = load_counts<CW>(counts, cell_off + c);
+    const uint2 n = load_counts<CW>(CountView{base, delta}, cell_off + c);
     out[c] = n.x;
     out[n_cells + c] = n.y;
 }
@@ -670,7 +723,7 @@ __global__ __launch_bounds__(256) void k_obs_cells(ObsArgs a)
     for (int k = 0; k < kObsQ; ++k) q[k] = NSum{0.0, 0.0};
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c < a.n_cells) {
-        const uint2 n = load_counts<CW>(a.counts, a.cell_off + c);
+        const uint2 n = load_counts<CW>(CountView{a.base, a.delta}, a.cell_off + c);
         const double pa = (double)n.x * a.phi_per_count, pb = (double)n.y * a.phi_per_count;
         const double inc = pa + pb - 1.0;
         double f;
@@ -752,13 +805,13 @@ hipError_t launch_fields(int cw, const FieldArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off, int64_t n_cells,
-                                uint32_t *out, hipStream_t st)
+hipError_t launch_unpack_counts(int cw, const uint32_t *base, const uint32_t *delta, int64_t cell_off,
+                                int64_t n_cells, uint32_t *out, hipStream_t st)
 {
     const int blocks = (int)((n_cells + 255) / 256);
     if (blocks == 0) return hipSuccess;
-    if (cw == COUNT_U16) hipLaunchKernelGGL((k_unpack_counts<COUNT_U16>), dim3(blocks), dim3(256), 0, st, counts, cell_off, n_cells, out);
-    else hipLaunchKernelGGL((k_unpack_counts<COUNT_U32>), dim3(blocks), dim3(256), 0, st, counts, cell_off, n_cells, out);
+    if (cw == COUNT_U16) hipLaunchKernelGGL((k_unpack_counts<COUNT_U16>), dim3(blocks), dim3(256), 0, st, base, delta, cell_off, n_cells, out);
+    else hipLaunchKernelGGL((k_unpack_counts<COUNT_U32>), dim3(blocks), dim3(256), 0, st, base, delta, cell_off, n_cells, out);
     return hipGetLastError();
 }
 

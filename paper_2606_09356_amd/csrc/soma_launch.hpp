@@ -16,13 +16,14 @@ struct SweepArgs {
     const uint32_t *chain_id;      // logical chain id per chain slot, or null for identity
     float *P0, *P1, *P2;           // coordinates (F32) or offsets (CELL)
     int *C0, *C1, *C2;             // cells (CELL only)
-    uint32_t *counts;              // three rotating count buffers
+    uint32_t *base;                // two rotating base-count buffers
+    uint32_t *delta;               // three rotating delta-count buffers
     int64_t count_words;           // uint32 words per buffer
     const float2 *omega;           // frozen fields, per cell (A, B)
     const uint64_t *sweep_ctr;     // sweeps done before this graph / launch sequence
     uint32_t rel;                  // sweep index relative to *sweep_ctr
     uint64_t seed;
-    unsigned long long *accept;    // per system
+    unsigned long long *accept;    // [n_sys][kAcceptSlots][kAcceptStride]
     uint32_t *status;
 };
 
@@ -40,7 +41,7 @@ struct FieldArgs {
     const DevSys *systems;
     int sys;
     int64_t n_cells;
-    const uint32_t *counts;        // the current buffer
+    const uint32_t *base, *delta;  // current counts = base + delta
     const float2 *omega;
     float *out;                    // [2][n_cells]
 };
@@ -66,7 +67,7 @@ struct ObsArgs {
     double k_half;
     const float *P0, *P1, *P2;
     const int *C0, *C1, *C2;
-    const uint32_t *counts;        // the current buffer
+    const uint32_t *base, *delta;  // current counts = base + delta
     int64_t cell_off, n_cells;
     double phi_per_count;          // M / B
     double chiN, kappaN;
@@ -78,8 +79,8 @@ struct ObsArgs {
 hipError_t launch_sweep(int repr, int cw, const SweepArgs &a, hipStream_t st);
 hipError_t launch_density(int repr, int cw, const DensityArgs &a, hipStream_t st);
 hipError_t launch_fields(int cw, const FieldArgs &a, hipStream_t st);
-hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off, int64_t n_cells,
-                                uint32_t *out, hipStream_t st);
+hipError_t launch_unpack_counts(int cw, const uint32_t *base, const uint32_t *delta, int64_t cell_off,
+                                int64_t n_cells, uint32_t *out, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_advance(uint64_t *ctr, uint32_t n, hipStream_t st);
 hipError_t launch_init(const InitArgs &a, hipStream_t st);

@@ -10,6 +10,12 @@ constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kMaxN = 128;             // beads per chain handled by one wave (2 beads per lane)
 constexpr int kPatternWords = kMaxN / 32;
 
+// Accepted-move counters: each system owns kAcceptSlots 64-bit counters one
+// cache line apart; wave w of a launch adds to slot (w mod kAcceptSlots), so
+// no single address takes more than 1/kAcceptSlots of the updates.
+constexpr int kAcceptSlots = 128;
+constexpr int kAcceptStride = 8;          // uint64 words between slots (64 B)
+
 enum Repr : int { REPR_F32 = 0, REPR_CELL = 1 };
 enum CountW : int { COUNT_U16 = 0, COUNT_U32 = 1 };
 

@@ -71,6 +71,10 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch brings its own HIP runtime (libamdhip64.so.7); importing it first
+    # makes the library bind to that same runtime, so torch streams and device
+    # pointers are valid in both and only one runtime owns the device.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
                           "(there is no CPU fallback)")
