@@ -255,6 +255,38 @@ __device__ __forceinline__ uint2 load_counts(const CountView &v, int64_t cell)
     }
 }
 
+// Raw base and delta words of one cell, loaded without being combined so that
+// several gathers can be in flight before the first use.
+struct RawCount {
+    uint32_t b0, d0, b1, d1;
+};
+
+template <int CW>
+__device__ __forceinline__ RawCount load_raw(const CountView &v, int64_t cell)
+{
+    RawCount r{0u, 0u, 0u, 0u};
+    if constexpr (CW == COUNT_U16) {
+        r.b0 = v.base[cell];
+        r.d0 = v.delta[cell];
+    } else {
+        const uint2 b = *reinterpret_cast<const uint2 *>(v.base + 2 * cell);
+        const uint2 d = *reinterpret_cast<const uint2 *>(v.delta + 2 * cell);
+        r.b0 = b.x; r.b1 = b.y; r.d0 = d.x; r.d1 = d.y;
+    }
+    return r;
+}
+
+template <int CW>
+__device__ __forceinline__ uint2 counts_of(const RawCount &r)
+{
+    if constexpr (CW == COUNT_U16) {
+        const uint32_t w = r.b0 + r.d0;
+        return make_uint2(w & 0xFFFFu, w >> 16);
+    } else {
+        return make_uint2(r.b0 + r.d0, r.b1 + r.d1);
+    }
+}
+
 // One bead of type t leaves cell `from` and enters cell `to` (non-returning
 // atomics; the count ranges are checked when the delta is folded).
 template <int CW>
@@ -370,34 +402,21 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a
 // The sweep kernel: even pass, odd pass, density scatter, clear of the
 // count buffer two sweeps ahead.  One launch per sweep for every system.
 // ---------------------------------------------------------------------------
+// One wave tile of the sweep: the even pass, the odd pass and the density
+// delta of up to G whole chains.
 template <int R, int CW>
-__global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
+__device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const CountView &cin,
+                                           uint32_t *dcur)
 {
     using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
-    const uint64_t s = *a.sweep_ctr + a.rel;
-    const int64_t W = a.count_words;
-    const CountView cin{a.base + ((s + 1) & 1) * W, a.delta + ((s + 2) % 3) * W};   // counts of sweep s
-    uint32_t *bcur = a.base + (s & 1) * W;
-    uint32_t *dcur = a.delta + (s % 3) * W;
-    uint32_t *dnext = a.delta + ((s + 1) % 3) * W;
-    bool fold_ovf = false;
-    {
-        const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < W; i += nthreads) {
-            uint32_t w;
-            fold_ovf |= fold_word<CW>(cin.base[i], cin.delta[i], w);
-            bcur[i] = w;
-            dnext[i] = 0u;
-        }
-    }
-    if (fold_ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
-    const int wave = wave_tile(a.waves_per_block, a.xcd_remap);
-    if (wave >= a.n_tiles) return;
     const Tile T = a.tiles[wave];
     const DevSys &S = a.systems[T.sys];
+    // per-system scalars, read once at the top so that divergent code below
+    // keeps them in SGPRs instead of re-reading the table
     const SysView v = make_view(S);
     const FieldCoef fc{S.cAA, S.cAB, S.cBA, S.cBB, S.c0};
     const bool frozen = S.frozen != 0;
+    const int64_t cell_off = S.cell_off;
     const int N = S.N, P = S.P;
     const int lane = (int)(threadIdx.x & 63);
     const int g = lane / P;
@@ -419,57 +438,63 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const Draw d0 = move_draw((uint32_t)i0, clog, (uint32_t)s, S.sys_id, k0, k1, S.delta);
     const Draw d1 = move_draw((uint32_t)i1, clog, (uint32_t)s, S.sys_id, k0, k1, S.delta);
     bool bad = false;
-    int cell0 = cell_of(b0, v, bad);
-    int cell1 = cell_of(b1, v, bad);
-    const int old0 = cell0, old1 = cell1;
+    const int old0 = cell_of(b0, v, bad);
+    const int old1 = cell_of(b1, v, bad);
+
+    // Both trial positions are known before either pass (the odd bead's
+    // proposal does not depend on the even pass), so the fields of all four
+    // cells are gathered together: one memory latency instead of two.
+    const Bead n0 = propose(b0, d0, v);
+    const Bead n1 = propose(b1, d1, v);
+    const int nc0 = cell_of(n0, v, bad);
+    const int nc1 = cell_of(n1, v, bad);
+    const bool g0 = active && nc0 != old0, g1 = has1 && nc1 != old1;
+    float dw0 = 0.0f, dw1 = 0.0f;
+    if (frozen) {
+        float2 wn0{0.f, 0.f}, wo0{0.f, 0.f}, wn1{0.f, 0.f}, wo1{0.f, 0.f};
+        if (g0) { wn0 = a.omega[cell_off + nc0]; wo0 = a.omega[cell_off + old0]; }
+        if (g1) { wn1 = a.omega[cell_off + nc1]; wo1 = a.omega[cell_off + old1]; }
+        dw0 = t0 ? wn0.y - wo0.y : wn0.x - wo0.x;
+        dw1 = t1 ? wn1.y - wo1.y : wn1.x - wo1.x;
+    } else {
+        RawCount rn0{0u, 0u, 0u, 0u}, ro0{0u, 0u, 0u, 0u}, rn1{0u, 0u, 0u, 0u}, ro1{0u, 0u, 0u, 0u};
+        if (g0) { rn0 = load_raw<CW>(cin, cell_off + nc0); ro0 = load_raw<CW>(cin, cell_off + old0); }
+        if (g1) { rn1 = load_raw<CW>(cin, cell_off + nc1); ro1 = load_raw<CW>(cin, cell_off + old1); }
+        if (g0) dw0 = omega_of(fc, counts_of<CW>(rn0), t0) - omega_of(fc, counts_of<CW>(ro0), t0);
+        if (g1) dw1 = omega_of(fc, counts_of<CW>(rn1), t1) - omega_of(fc, counts_of<CW>(ro1), t1);
+    }
     const float kh = S.k_half;
 
     // even pass: bead 2p, neighbours 2p-1 (previous lane's odd bead) and 2p+1
-    bool acc0 = false;
+    bool acc0;
     {
         const Bead left = shfl_up1(b1);
-        const Bead n0 = propose(b0, d0, v);
         const float3 de = bond(n0, b0, v);
         const float dd = dot3(de, de);
         float dE = 0.0f;
         if (p > 0) dE += 2.0f * dot3(de, bond(b0, left, v)) + dd;
         if (i1 < N) dE += 2.0f * dot3(de, bond(b0, b1, v)) + dd;
-        dE *= kh;
-        const int nc = cell_of(n0, v, bad);
-        if (nc != cell0)
-            dE += omega_at<CW>(frozen, a.omega, cin, S.cell_off, nc, t0, fc) -
-                  omega_at<CW>(frozen, a.omega, cin, S.cell_off, cell0, t0, fc);
+        dE = dE * kh + dw0;
         acc0 = active && (d0.u < expf(-dE));
-        if (acc0) {
-            b0 = n0;
-            cell0 = nc;
-        }
+        if (acc0) b0 = n0;
     }
     // odd pass: bead 2p+1, neighbours 2p (this lane, updated) and 2p+2 (next lane)
-    bool acc1 = false;
+    bool acc1;
     {
         const Bead right = shfl_down1(b0);
-        const Bead n1 = propose(b1, d1, v);
         const float3 de = bond(n1, b1, v);
         const float dd = dot3(de, de);
         float dE = 2.0f * dot3(de, bond(b1, b0, v)) + dd;
         if (i1 + 1 < N) dE += 2.0f * dot3(de, bond(b1, right, v)) + dd;
-        dE *= kh;
-        const int nc = cell_of(n1, v, bad);
-        if (has1 && nc != cell1)
-            dE += omega_at<CW>(frozen, a.omega, cin, S.cell_off, nc, t1, fc) -
-                  omega_at<CW>(frozen, a.omega, cin, S.cell_off, cell1, t1, fc);
+        dE = dE * kh + dw1;
         acc1 = has1 && (d1.u < expf(-dE));
-        if (acc1) {
-            b1 = n1;
-            cell1 = nc;
-        }
+        if (acc1) b1 = n1;
     }
     if (active) store_pair(A, slot, b0, b1);
 
     // density delta: only beads that changed cell
-    if (acc0 && cell0 != old0) move_count<CW>(dcur, S.cell_off + old0, S.cell_off + cell0, t0);
-    if (acc1 && cell1 != old1) move_count<CW>(dcur, S.cell_off + old1, S.cell_off + cell1, t1);
+    if (acc0 && nc0 != old0) move_count<CW>(dcur, cell_off + old0, cell_off + nc0, t0);
+    if (acc1 && nc1 != old1) move_count<CW>(dcur, cell_off + old1, cell_off + nc1, t1);
 
     const uint64_t nacc = __popcll(__ballot(acc0)) + __popcll(__ballot(acc1));
     const bool any_bad = __ballot(active && bad) != 0;
@@ -481,8 +506,44 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     }
 }
 
-// Density of the current positions into a zeroed count buffer (creation,
-// soma_set_positions / soma_set_state).  Same tile mapping as the sweep.
+// The sweep kernel: one launch per sweep for every system.  Each wave moves
+// one tile; every thread also folds (at most a few) count words of the
+// previous sweep, with the fold's loads issued before the move work and its
+// stores after it.
+template <int R, int CW>
+__global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
+{
+    const uint64_t s = *a.sweep_ctr + a.rel;
+    const int64_t W = a.count_words;
+    const CountView cin{a.base + ((s + 1) & 1) * W, a.delta + ((s + 2) % 3) * W};   // counts of sweep s
+    uint32_t *bcur = a.base + (s & 1) * W;
+    uint32_t *dcur = a.delta + (s % 3) * W;
+    uint32_t *dnext = a.delta + ((s + 1) % 3) * W;
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    uint32_t fb = 0u, fd = 0u;
+    if (gtid < W) {
+        fb = cin.base[gtid];
+        fd = cin.delta[gtid];
+    }
+    const int wave = wave_tile(a.waves_per_block, a.xcd_remap);
+    if (wave < a.n_tiles) sweep_tile<R, CW>(a, wave, s, cin, dcur);
+    bool fold_ovf = false;
+    if (gtid < W) {
+        uint32_t w;
+        fold_ovf |= fold_word<CW>(fb, fd, w);
+        bcur[gtid] = w;
+        dnext[gtid] = 0u;
+    }
+    for (int64_t i = gtid + nthreads; i < W; i += nthreads) {
+        uint32_t w;
+        fold_ovf |= fold_word<CW>(cin.base[i], cin.delta[i], w);
+        bcur[i] = w;
+        dnext[i] = 0u;
+    }
+    if (fold_ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
+}
+
 template <int R, int CW>
 __global__ __launch_bounds__(256) void k_density(DensityArgs a)
 {
