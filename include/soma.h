@@ -75,8 +75,8 @@ enum { SOMA_HAM_HELFAND = 0, SOMA_HAM_CHI_AB = 1 };
  * pattern_a, chains [n_chains_a, n_chains) those of pattern_b (0 = A,
  * 1 = B): a diblock or triblock melt sets n_chains_a = n_chains, an A/B
  * homopolymer blend an all-A pattern_a and an all-B pattern_b.
- * Limits: 2 <= N <= 128; grid[d] >= 1; the cell edge box[d]/grid[d] must be
- * larger than move_halfwidth. */
+ * Limits: 2 <= N <= 128; 1 <= grid[d] <= 32768 with grid[0] * grid[1] <= 2^24;
+ * move_halfwidth below 0.99 cell edges box[d]/grid[d]. */
 typedef struct {
     int32_t n_chains;
     int32_t N;                 /* beads per chain */
@@ -98,7 +98,9 @@ typedef struct {
     int32_t use_graph;         /* nonzero: soma_mc_sweep replays a captured hipGraph per sweep count */
     int32_t density_mode;      /* 0: global atomics, 1: LDS-privatised window, -1: pick by timing at create */
     int32_t reorder_every;     /* >0: spatially sort chains every this many sweeps; 0: never */
-    int32_t waves_per_block;   /* 1..16 wave tiles per workgroup; 0: library default */
+    int32_t waves_per_block;   /* 1..16 waves per workgroup; 0: library default */
+    int32_t waves_per_cu;      /* >0: sweep grid of this many waves per compute unit, each wave
+                                  moving a contiguous range of tiles; 0: one tile per wave */
     int32_t sys_id_base;       /* system k draws with Philox counter word sys_id_base + k (< 2^31);
                                   a system run alone with sys_id_base = k repeats its batched run */
     void *hip_stream;          /* hipStream_t, NULL for the null stream */

@@ -5,6 +5,7 @@
 // Every step of the sweep runs in the HIP kernels of soma_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -25,8 +26,8 @@ namespace {
 thread_local std::string g_create_error;
 
 struct Layout {
-    size_t systems, tiles, chain_id, P[3], C[3], base, delta, omega, accept, status, partials, obs_out,
-        staging, total;
+    size_t systems, tiles, chain_id, chain_id2, P[3], C[3], Q[3], D[3], keys, hist, bsum, perm, base, delta,
+        omega, accept, status, partials, obs_out, staging, total;
     int64_t total_slots = 0, total_cells = 0, total_chains = 0, count_words = 0;
     int n_tiles = 0;
     int64_t max_obs_blocks = 0, max_cells = 0;
@@ -52,8 +53,9 @@ struct soma_ctx {
     char *ws = nullptr;
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
-    int repr = 0, cw = 0, waves_per_block = 4, xcd_remap = 1, density_mode = 0;
+    int repr = 0, cw = 0, waves_per_block = 4, xcd_remap = 1, density_mode = 0, max_blocks = 0;
     uint64_t sweep = 0;
+    uint64_t last_reorder = ~uint64_t(0);
     int latched = SOMA_OK;
     std::string err;
     std::map<int, hipGraphExec_t> graphs;
@@ -63,6 +65,10 @@ struct soma_ctx {
     Tile *d_tiles() const { return reinterpret_cast<Tile *>(ws + L.tiles); }
     float *P(int d) const { return reinterpret_cast<float *>(ws + L.P[d]); }
     int *C(int d) const { return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + L.C[d]) : nullptr; }
+    float *Q(int d) const { return reinterpret_cast<float *>(ws + L.Q[d]); }
+    int *D(int d) const { return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + L.D[d]) : nullptr; }
+    uint32_t *chain_id() const { return reinterpret_cast<uint32_t *>(ws + L.chain_id); }
+    uint32_t *u32(size_t off) const { return reinterpret_cast<uint32_t *>(ws + off); }
     // Counts after S sweeps are base[(S-1) mod 2] + delta[(S-1) mod 3].
     uint32_t *base() const { return reinterpret_cast<uint32_t *>(ws + L.base); }
     uint32_t *delta() const { return reinterpret_cast<uint32_t *>(ws + L.delta); }
@@ -107,6 +113,7 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
     if (opt->pos_repr != SOMA_POS_F32 && opt->pos_repr != SOMA_POS_CELL_F32) { msg = "bad pos_repr"; return SOMA_EINVAL; }
     if (opt->count_width != SOMA_COUNT_U16 && opt->count_width != SOMA_COUNT_U32) { msg = "bad count_width"; return SOMA_EINVAL; }
     if (opt->waves_per_block < 0 || opt->waves_per_block > 16) { msg = "waves_per_block must be 0..16"; return SOMA_EINVAL; }
+    if (opt->waves_per_cu < 0 || opt->waves_per_cu > 64) { msg = "waves_per_cu must be 0..64"; return SOMA_EINVAL; }
     if (opt->density_mode < -1 || opt->density_mode > 1) { msg = "density_mode must be -1, 0 or 1"; return SOMA_EINVAL; }
     if (opt->reorder_every < 0) { msg = "reorder_every must be >= 0"; return SOMA_EINVAL; }
     if (opt->sys_id_base < 0 || (int64_t)opt->sys_id_base + n_sys >= (int64_t(1) << 31)) { msg = "sys_id_base + n_sys must stay below 2^31"; return SOMA_EINVAL; }
@@ -132,9 +139,11 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
             if (d.grid[a] < 1 || d.grid[a] > (1 << 15)) return bad("grid must be in [1, 32768]");
             cells *= d.grid[a];
             const double edge = d.box[a] / d.grid[a];
-            if (!(d.move_halfwidth > 0) || !(d.move_halfwidth < edge)) return bad("move_halfwidth must be in (0, cell edge)");
+            if (!(d.move_halfwidth > 0) || !(d.move_halfwidth < 0.99 * edge))
+                return bad("move_halfwidth must be in (0, 0.99 cell edge)");
         }
         if (cells >= (int64_t(1) << 31)) return bad("too many cells");
+        if ((int64_t)d.grid[0] * d.grid[1] > (int64_t(1) << 24)) return bad("grid[0] * grid[1] must be <= 2^24");
     }
     return SOMA_OK;
 }
@@ -180,6 +189,7 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
             const double k_spring = 3.0 * (d.N - 1) / (d.Re * d.Re);
             v.k_half = (float)(0.5 * k_spring);
             v.delta = (float)d.move_halfwidth;
+            v.inv_P = (float)(1.0 / P);
             const double s = (double)M / ((double)d.n_chains * d.N);   // phi per count
             const double inv_n = 1.0 / d.N;
             if (d.ham_form == SOMA_HAM_HELFAND) {
@@ -223,8 +233,16 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     L.systems = take(sizeof(DevSys) * n_sys);
     L.tiles = take(sizeof(Tile) * tiles);
     L.chain_id = take(sizeof(uint32_t) * chains);
+    L.chain_id2 = take(sizeof(uint32_t) * chains);
     for (int a = 0; a < 3; ++a) L.P[a] = take(sizeof(float) * slots);
     for (int a = 0; a < 3; ++a) L.C[a] = cell ? take(sizeof(int) * slots) : 0;
+    // spatial reorder: scratch positions, keys, histogram / offsets, permutation
+    for (int a = 0; a < 3; ++a) L.Q[a] = take(sizeof(float) * slots);
+    for (int a = 0; a < 3; ++a) L.D[a] = cell ? take(sizeof(int) * slots) : 0;
+    L.keys = take(sizeof(uint32_t) * chains);
+    L.hist = take(sizeof(uint32_t) * cells);
+    L.bsum = take(sizeof(uint32_t) * soma::reorder_bsum_words(cells));
+    L.perm = take(sizeof(uint32_t) * chains);
     L.base = take(sizeof(uint32_t) * 2 * L.count_words);
     L.delta = take(sizeof(uint32_t) * 3 * L.count_words);
     L.omega = take(sizeof(float) * 2 * cells);
@@ -259,6 +277,7 @@ int sync_status(soma_ctx *c)
     if (st & soma::ST_COUNT_OVERFLOW) { c->latched = SOMA_EOVERFLOW; return fail(c, SOMA_EOVERFLOW, "density count exceeded its width"); }
     if (st & soma::ST_CELL_OVERFLOW) { c->latched = SOMA_EOVERFLOW; return fail(c, SOMA_EOVERFLOW, "bead cell index left the int32 range (or a coordinate is not finite)"); }
     if (st & soma::ST_NONFINITE) { c->latched = SOMA_ENONFINITE; return fail(c, SOMA_ENONFINITE, "non-finite field value"); }
+    if (st & soma::ST_INTERNAL) { c->latched = SOMA_EDEVICE; return fail(c, SOMA_EDEVICE, "internal consistency check failed in the chain reorder"); }
     return SOMA_OK;
 }
 
@@ -269,8 +288,9 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
     a.tiles = c->d_tiles();
     a.n_tiles = c->L.n_tiles;
     a.waves_per_block = c->waves_per_block;
+    a.max_blocks = c->max_blocks;
     a.xcd_remap = c->xcd_remap;
-    a.chain_id = nullptr;
+    a.chain_id = c->chain_id();
     for (int d = 0; d < 3; ++d) {
         (&a.P0)[d] = c->P(d);
         (&a.C0)[d] = c->C(d);
@@ -315,6 +335,7 @@ int rebuild_density(soma_ctx *c, int32_t sys)
         (&d.C0)[k] = c->C(k);
     }
     d.counts = cur;
+    d.chain_id = c->chain_id();
     d.status = c->status();
     HIPCHK(c, soma::launch_density(c->repr, c->cw, d, c->stream));
     return SOMA_OK;
@@ -323,6 +344,48 @@ int rebuild_density(soma_ctx *c, int32_t sys)
 int upload_sys(soma_ctx *c, int32_t sys)
 {
     HIPCHK(c, hipMemcpyAsync(c->d_sys() + sys, &c->sys[sys].dev, sizeof(DevSys), hipMemcpyHostToDevice, c->stream));
+    return SOMA_OK;
+}
+
+soma::ReorderArgs reorder_args(const soma_ctx *c)
+{
+    soma::ReorderArgs r{};
+    r.systems = c->d_sys();
+    r.tiles = c->d_tiles();
+    r.n_tiles = c->L.n_tiles;
+    r.total_chains = c->L.total_chains;
+    r.total_cells = c->L.total_cells;
+    for (int d = 0; d < 3; ++d) {
+        (&r.P0)[d] = c->P(d);
+        (&r.C0)[d] = c->C(d);
+        (&r.Q0)[d] = c->Q(d);
+        (&r.D0)[d] = c->D(d);
+    }
+    r.chain_id = c->chain_id();
+    r.chain_id2 = c->u32(c->L.chain_id2);
+    r.keys = c->u32(c->L.keys);
+    r.hist = c->u32(c->L.hist);
+    r.bsum = c->u32(c->L.bsum);
+    r.perm = c->u32(c->L.perm);
+    r.status = c->status();
+    return r;
+}
+
+// Sort the chains of every system by the cell of their first bead and move
+// positions and logical ids into that order (eager launches, never captured).
+int reorder_chains(soma_ctx *c)
+{
+    const soma::ReorderArgs r = reorder_args(c);
+    HIPCHK(c, soma::launch_reorder(c->repr, r, c->stream));
+    const size_t n = sizeof(float) * (size_t)c->L.total_slots;
+    for (int d = 0; d < 3; ++d) {
+        HIPCHK(c, hipMemcpyAsync(c->P(d), c->Q(d), n, hipMemcpyDeviceToDevice, c->stream));
+        if (c->repr == soma::REPR_CELL)
+            HIPCHK(c, hipMemcpyAsync(c->C(d), c->D(d), n, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->chain_id(), r.chain_id2, sizeof(uint32_t) * (size_t)c->L.total_chains,
+                             hipMemcpyDeviceToDevice, c->stream));
+    c->last_reorder = c->sweep;
     return SOMA_OK;
 }
 
@@ -385,31 +448,62 @@ void quantise_host(const soma_ctx *c, const HostSys &h, const double *xyz, std::
     }
 }
 
-int download_slots(soma_ctx *c, const HostSys &h, std::vector<float> (&P)[3], std::vector<int> (&Cv)[3])
+// Logical chain id of every chain slot of one system.
+int fetch_chain_ids(soma_ctx *c, const HostSys &h, std::vector<uint32_t> &cid)
 {
-    const size_t n = (size_t)h.d.n_chains * 2 * h.dev.P;
-    for (int a = 0; a < 3; ++a) {
-        P[a].resize(n);
-        HIPCHK(c, hipMemcpyAsync(P[a].data(), c->P(a) + h.dev.slot_off, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-        if (c->repr == soma::REPR_CELL) {
-            Cv[a].resize(n);
-            HIPCHK(c, hipMemcpyAsync(Cv[a].data(), c->C(a) + h.dev.slot_off, n * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        }
-    }
+    cid.resize((size_t)h.d.n_chains);
+    HIPCHK(c, hipMemcpyAsync(cid.data(), c->chain_id() + h.dev.chain_off, sizeof(uint32_t) * cid.size(),
+                             hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (uint32_t v : cid)
+        if (v >= (uint32_t)h.d.n_chains) return fail(c, SOMA_EDEVICE, "corrupt chain id table");
     return SOMA_OK;
 }
 
+// Stored slots of one system in logical chain order (chain L at L * stride).
+int download_slots(soma_ctx *c, const HostSys &h, std::vector<float> (&P)[3], std::vector<int> (&Cv)[3])
+{
+    const size_t stride = 2 * (size_t)h.dev.P, n = (size_t)h.d.n_chains * stride;
+    std::vector<uint32_t> cid;
+    int rc = fetch_chain_ids(c, h, cid);
+    if (rc != SOMA_OK) return rc;
+    std::vector<float> fp(n);
+    std::vector<int> ip(n);
+    for (int a = 0; a < 3; ++a) {
+        HIPCHK(c, hipMemcpyAsync(fp.data(), c->P(a) + h.dev.slot_off, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        if (c->repr == soma::REPR_CELL)
+            HIPCHK(c, hipMemcpyAsync(ip.data(), c->C(a) + h.dev.slot_off, n * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        P[a].resize(n);
+        if (c->repr == soma::REPR_CELL) Cv[a].resize(n);
+        for (size_t j = 0; j < cid.size(); ++j) {
+            std::memcpy(&P[a][cid[j] * stride], &fp[j * stride], stride * sizeof(float));
+            if (c->repr == soma::REPR_CELL) std::memcpy(&Cv[a][cid[j] * stride], &ip[j * stride], stride * sizeof(int));
+        }
+    }
+    return SOMA_OK;
+}
+
+// Upload slots given in logical chain order to the current physical order.
 int upload_slots(soma_ctx *c, const HostSys &h, const std::vector<float> (&P)[3], const std::vector<int> (&Cv)[3])
 {
-    const size_t n = (size_t)h.d.n_chains * 2 * h.dev.P;
+    const size_t stride = 2 * (size_t)h.dev.P, n = (size_t)h.d.n_chains * stride;
+    std::vector<uint32_t> cid;
+    int rc = fetch_chain_ids(c, h, cid);
+    if (rc != SOMA_OK) return rc;
+    std::vector<float> fp(n);
+    std::vector<int> ip(n);
     for (int a = 0; a < 3; ++a) {
-        HIPCHK(c, hipMemcpyAsync(c->P(a) + h.dev.slot_off, P[a].data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        for (size_t j = 0; j < cid.size(); ++j) {
+            std::memcpy(&fp[j * stride], &P[a][cid[j] * stride], stride * sizeof(float));
+            if (c->repr == soma::REPR_CELL) std::memcpy(&ip[j * stride], &Cv[a][cid[j] * stride], stride * sizeof(int));
+        }
+        HIPCHK(c, hipMemcpyAsync(c->P(a) + h.dev.slot_off, fp.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
         if (c->repr == soma::REPR_CELL)
-            HIPCHK(c, hipMemcpyAsync(c->C(a) + h.dev.slot_off, Cv[a].data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->C(a) + h.dev.slot_off, ip.data(), n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        // the staging vectors are reused: wait for the copies of this axis
+        HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    // host vectors must stay alive until the copies complete
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     return SOMA_OK;
 }
 
@@ -444,6 +538,15 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
     c->waves_per_block = opt->waves_per_block > 0 ? opt->waves_per_block : 4;
     c->density_mode = 0;
     c->stream = reinterpret_cast<hipStream_t>(opt->hip_stream);
+    if (opt->waves_per_cu > 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+            delete c;
+            return fail(nullptr, SOMA_EDEVICE, "cannot query the compute-unit count");
+        }
+        c->max_blocks = std::max(1, opt->waves_per_cu * cus / c->waves_per_block);
+    }
     c->L = plan(sys, n_sys, opt, &c->sys);
     if (workspace_bytes < c->L.total) {
         char b[128];
@@ -476,6 +579,8 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
              return (int)SOMA_OK;
          }()) != SOMA_OK)
         return bail(rc);
+    if ((e = soma::launch_iota_chains(reorder_args(c), c->stream)) != hipSuccess)
+        return bail(hip_fail(c, e, "chain ids"));
     for (const HostSys &h : c->sys) {
         soma::InitArgs ia{};
         ia.repr = c->repr;
@@ -495,6 +600,7 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
         if ((e = soma::launch_init(ia, c->stream)) != hipSuccess) return bail(hip_fail(c, e, "init kernel"));
     }
     if ((rc = rebuild_density(c, -1)) != SOMA_OK) return bail(rc);
+    if (opt->reorder_every > 0 && (rc = reorder_chains(c)) != SOMA_OK) return bail(rc);
     if ((rc = sync_status(c)) != SOMA_OK) return bail(rc);
     *out = c;
     return SOMA_OK;
@@ -516,20 +622,26 @@ int soma_mc_sweep(soma_ctx *c, int32_t n)
     int rc = check_ctx(c);
     if (rc != SOMA_OK) return rc;
     if (n < 0) return fail(c, SOMA_EINVAL, "n_sweeps must be >= 0");
-    if (n == 0) return SOMA_OK;
-    if (c->opt.use_graph) {
-        int32_t left = n;
-        while (left > 0) {
-            const int32_t chunk = left > kGraphChunk ? kGraphChunk : left;
+    const uint64_t R = (uint64_t)c->opt.reorder_every;
+    int32_t left = n;
+    while (left > 0) {
+        // reorders happen at sweep counts that are multiples of R, however
+        // the sweeps are split over calls
+        if (R > 0 && c->sweep % R == 0 && c->last_reorder != c->sweep)
+            if ((rc = reorder_chains(c)) != SOMA_OK) return rc;
+        int32_t seg = left;
+        if (R > 0) seg = (int32_t)std::min<uint64_t>((uint64_t)left, R - c->sweep % R);
+        if (seg > kGraphChunk) seg = kGraphChunk;
+        if (c->opt.use_graph) {
             hipGraphExec_t ex;
-            if ((rc = graph_for(c, chunk, &ex)) != SOMA_OK) return rc;
+            if ((rc = graph_for(c, seg, &ex)) != SOMA_OK) return rc;
             HIPCHK(c, hipGraphLaunch(ex, c->stream));
-            left -= chunk;
+        } else {
+            if ((rc = record_sweeps(c, seg, c->stream)) != SOMA_OK) return rc;
         }
-    } else {
-        if ((rc = record_sweeps(c, n, c->stream)) != SOMA_OK) return rc;
+        c->sweep += (uint64_t)seg;
+        left -= seg;
     }
-    c->sweep += (uint64_t)n;
     return SOMA_OK;
 }
 

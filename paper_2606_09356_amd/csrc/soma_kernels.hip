@@ -62,26 +62,36 @@ struct Draw {
 
 // Top 24 bits of each word: displacement = delta * ((w >> 8) - 2^23) * 2^-23
 // (one FP32 multiply of exact operands), acceptance variate u = (w >> 8) 2^-24.
+// delta_s = delta * 2^-23 (exact), so delta_s * m rounds exactly like
+// delta * (m * 2^-23): one FP32 rounding of the same real product.
 __device__ __forceinline__ Draw move_draw(uint32_t bead, uint32_t chain, uint32_t sweep,
-                                          uint32_t sys, uint32_t k0, uint32_t k1, float delta)
+                                          uint32_t sys, uint32_t k0, uint32_t k1, float delta_s)
 {
     const uint4 w = philox4x32_10(make_uint4(bead, chain, sweep, sys), k0, k1);
     Draw d;
-    d.dx = delta * ((float)((int)(w.x >> 8) - 8388608) * 0x1p-23f);
-    d.dy = delta * ((float)((int)(w.y >> 8) - 8388608) * 0x1p-23f);
-    d.dz = delta * ((float)((int)(w.z >> 8) - 8388608) * 0x1p-23f);
+    d.dx = delta_s * (float)((int)(w.x >> 8) - 8388608);
+    d.dy = delta_s * (float)((int)(w.y >> 8) - 8388608);
+    d.dz = delta_s * (float)((int)(w.z >> 8) - 8388608);
     d.u = (float)(w.w >> 8) * 0x1p-24f;
     return d;
 }
 
-// Periodic wrap of an unwrapped cell index into [0, n); exact for |i| < 2^24.
+// Periodic wrap of an unwrapped cell index into [0, n); exact for |i| < 2^23
+// (24-bit multiply: |q| < 2^23, n < 2^15).
 __device__ __forceinline__ int wrap_cell(int i, int n, float inv_n)
 {
     const int q = (int)floorf((float)i * inv_n);
-    int r = i - q * n;
+    int r = i - __mul24(q, n);
     r = r < 0 ? r + n : r;
     r = r >= n ? r - n : r;
     return r;
+}
+
+// Wrap of i in [-n, 2n) into [0, n).
+__device__ __forceinline__ int wrap_step(int i, int n)
+{
+    i = i < 0 ? i + n : i;
+    return i >= n ? i - n : i;
 }
 
 // ---------------------------------------------------------------------------
@@ -139,32 +149,82 @@ __device__ __forceinline__ BeadCell propose(const BeadCell &a, const Draw &d, co
     return n;
 }
 
-// Linear NGP cell of a bead; sets `bad` when the unwrapped index leaves the
-// range the wrap handles (or the coordinate is not finite).
-__device__ __forceinline__ int cell_of(const BeadF32 &a, const SysView &v, bool &bad)
+// NGP cell of a bead: wrapped cell coordinates and, for FP32 positions, the
+// unwrapped floors (to step to the cell of a trial position).  `bad` is set
+// when the unwrapped index leaves the range the wrap handles (or the
+// coordinate is not finite); the bead is then counted in cell 0.
+struct CellPos {
+    int x, y, z;
+    float fx, fy, fz;
+};
+
+__device__ __forceinline__ CellPos locate(const BeadF32 &a, const SysView &v, bool &bad)
 {
-    const float fx = floorf(a.x * v.ie0), fy = floorf(a.y * v.ie1), fz = floorf(a.z * v.ie2);
+    CellPos c;
+    c.fx = floorf(a.x * v.ie0);
+    c.fy = floorf(a.y * v.ie1);
+    c.fz = floorf(a.z * v.ie2);
     const float lim = (float)kCellLimit;
-    if (!(fabsf(fx) < lim && fabsf(fy) < lim && fabsf(fz) < lim)) {
+    if (!(fabsf(c.fx) < lim && fabsf(c.fy) < lim && fabsf(c.fz) < lim)) {
         bad = true;
-        return 0;
+        c.x = c.y = c.z = 0;
+        c.fx = c.fy = c.fz = 0.0f;
+        return c;
     }
-    const int ix = wrap_cell((int)fx, v.n0, v.inv_n0);
-    const int iy = wrap_cell((int)fy, v.n1, v.inv_n1);
-    const int iz = wrap_cell((int)fz, v.n2, v.inv_n2);
-    return (ix * v.n1 + iy) * v.n2 + iz;
+    c.x = wrap_cell((int)c.fx, v.n0, v.inv_n0);
+    c.y = wrap_cell((int)c.fy, v.n1, v.inv_n1);
+    c.z = wrap_cell((int)c.fz, v.n2, v.inv_n2);
+    return c;
 }
-__device__ __forceinline__ int cell_of(const BeadCell &a, const SysView &v, bool &bad)
+__device__ __forceinline__ CellPos locate(const BeadCell &a, const SysView &v, bool &bad)
 {
+    CellPos c{0, 0, 0, 0.0f, 0.0f, 0.0f};
     if (a.cx <= -kCellLimit || a.cx >= kCellLimit || a.cy <= -kCellLimit || a.cy >= kCellLimit ||
         a.cz <= -kCellLimit || a.cz >= kCellLimit) {
         bad = true;
-        return 0;
+        return c;
     }
-    const int ix = wrap_cell(a.cx, v.n0, v.inv_n0);
-    const int iy = wrap_cell(a.cy, v.n1, v.inv_n1);
-    const int iz = wrap_cell(a.cz, v.n2, v.inv_n2);
-    return (ix * v.n1 + iy) * v.n2 + iz;
+    c.x = wrap_cell(a.cx, v.n0, v.inv_n0);
+    c.y = wrap_cell(a.cy, v.n1, v.inv_n1);
+    c.z = wrap_cell(a.cz, v.n2, v.inv_n2);
+    return c;
+}
+
+// Cell of a trial position.  The move half-width is below 0.99 cell edges,
+// so the unwrapped index changes by at most one per axis (clamped so that a
+// non-finite coordinate still yields an in-range cell).
+__device__ __forceinline__ int clamp1(int k) { return k < -1 ? -1 : (k > 1 ? 1 : k); }
+
+__device__ __forceinline__ CellPos step(const CellPos &o, const BeadF32 &, const BeadF32 &n, const SysView &v)
+{
+    CellPos c;
+    c.fx = floorf(n.x * v.ie0);
+    c.fy = floorf(n.y * v.ie1);
+    c.fz = floorf(n.z * v.ie2);
+    c.x = wrap_step(o.x + clamp1((int)(c.fx - o.fx)), v.n0);
+    c.y = wrap_step(o.y + clamp1((int)(c.fy - o.fy)), v.n1);
+    c.z = wrap_step(o.z + clamp1((int)(c.fz - o.fz)), v.n2);
+    return c;
+}
+__device__ __forceinline__ CellPos step(const CellPos &o, const BeadCell &ob, const BeadCell &n, const SysView &v)
+{
+    CellPos c{0, 0, 0, 0.0f, 0.0f, 0.0f};
+    c.x = wrap_step(o.x + clamp1(n.cx - ob.cx), v.n0);
+    c.y = wrap_step(o.y + clamp1(n.cy - ob.cy), v.n1);
+    c.z = wrap_step(o.z + clamp1(n.cz - ob.cz), v.n2);
+    return c;
+}
+
+// Linear index (x * ny + y) * nz + z with 24-bit multiplies (nx * ny <= 2^24).
+__device__ __forceinline__ int lin(const CellPos &c, const SysView &v)
+{
+    return (int)__umul24((uint32_t)(__umul24((uint32_t)c.x, (uint32_t)v.n1) + c.y), (uint32_t)v.n2) + c.z;
+}
+
+template <class Bead>
+__device__ __forceinline__ int cell_of(const Bead &a, const SysView &v, bool &bad)
+{
+    return lin(locate(a, v, bad), v);
 }
 
 __device__ __forceinline__ BeadF32 shfl_up1(const BeadF32 &a)
@@ -402,13 +462,32 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a
 // The sweep kernel: even pass, odd pass, density scatter, clear of the
 // count buffer two sweeps ahead.  One launch per sweep for every system.
 // ---------------------------------------------------------------------------
-// One wave tile of the sweep: the even pass, the odd pass and the density
-// delta of up to G whole chains.
-template <int R, int CW>
-__device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const CountView &cin,
-                                           uint32_t *dcur)
+// Issue the position loads of one wave tile (lane p of chain g holds beads
+// 2p and 2p+1); used to prefetch the next tile while the current one moves.
+template <class Bead>
+__device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0, Bead &b1)
 {
-    using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
+    const Tile T = a.tiles[tile];
+    const DevSys &S = a.systems[T.sys];
+    const int P = S.P;
+    const int lane = (int)(threadIdx.x & 63);
+    const int g = (int)(((float)lane + 0.5f) * S.inv_P);
+    const int p = lane - g * P;
+    const int nin = min(S.G, S.n_chains - (int)T.chain0);
+    b0 = Bead{};
+    b1 = Bead{};
+    if (g < nin) {
+        const int64_t slot = S.slot_off + (int64_t)((int)T.chain0 + g) * (2 * P) + 2 * p;
+        load_pair(PosArrays{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2}, slot, b0, b1);
+    }
+}
+
+// One wave tile of the sweep: the even pass, the odd pass and the density
+// delta of up to G whole chains, from positions already loaded by tile_load.
+template <int R, int CW, class Bead>
+__device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const CountView &cin,
+                                           uint32_t *dcur, Bead b0, Bead b1)
+{
     const Tile T = a.tiles[wave];
     const DevSys &S = a.systems[T.sys];
     // per-system scalars, read once at the top so that divergent code below
@@ -419,7 +498,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     const int64_t cell_off = S.cell_off;
     const int N = S.N, P = S.P;
     const int lane = (int)(threadIdx.x & 63);
-    const int g = lane / P;
+    // lane / P: (lane + 1/2) / P is at least 1/(2P) from an integer, far more
+    // than the FP32 error of the product
+    const int g = (int)(((float)lane + 0.5f) * S.inv_P);
     const int p = lane - g * P;
     const int nin = min(S.G, S.n_chains - (int)T.chain0);
     const bool active = g < nin;
@@ -429,25 +510,28 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     const int64_t slot = S.slot_off + (int64_t)chain * (2 * P) + i0;
     const PosArrays A{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2};
 
-    Bead b0{}, b1{};
-    if (active) load_pair(A, slot, b0, b1);
-    const uint32_t clog = a.chain_id ? a.chain_id[S.chain_off + chain] : (uint32_t)chain;
-    const int t0 = pattern_type(S, chain, i0);
-    const int t1 = pattern_type(S, chain, i1 < N ? i1 : i0);
+    // logical chain id: keys the random numbers and picks the species, so
+    // results do not depend on where a chain sits in memory
+    const uint32_t clog = a.chain_id[S.chain_off + chain];
+    const int t0 = pattern_type(S, (int)clog, i0);
+    const int t1 = pattern_type(S, (int)clog, i1 < N ? i1 : i0);
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const Draw d0 = move_draw((uint32_t)i0, clog, (uint32_t)s, S.sys_id, k0, k1, S.delta);
-    const Draw d1 = move_draw((uint32_t)i1, clog, (uint32_t)s, S.sys_id, k0, k1, S.delta);
+    const float delta_s = S.delta * 0x1p-23f;
+    const Draw d0 = move_draw((uint32_t)i0, clog, (uint32_t)s, S.sys_id, k0, k1, delta_s);
+    const Draw d1 = move_draw((uint32_t)i1, clog, (uint32_t)s, S.sys_id, k0, k1, delta_s);
     bool bad = false;
-    const int old0 = cell_of(b0, v, bad);
-    const int old1 = cell_of(b1, v, bad);
+    const CellPos c0 = locate(b0, v, bad);
+    const CellPos c1 = locate(b1, v, bad);
+    const int old0 = lin(c0, v);
+    const int old1 = lin(c1, v);
 
     // Both trial positions are known before either pass (the odd bead's
     // proposal does not depend on the even pass), so the fields of all four
     // cells are gathered together: one memory latency instead of two.
     const Bead n0 = propose(b0, d0, v);
     const Bead n1 = propose(b1, d1, v);
-    const int nc0 = cell_of(n0, v, bad);
-    const int nc1 = cell_of(n1, v, bad);
+    const int nc0 = lin(step(c0, b0, n0, v), v);
+    const int nc1 = lin(step(c1, b1, n1, v), v);
     const bool g0 = active && nc0 != old0, g1 = has1 && nc1 != old1;
     float dw0 = 0.0f, dw1 = 0.0f;
     if (frozen) {
@@ -475,7 +559,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
         if (p > 0) dE += 2.0f * dot3(de, bond(b0, left, v)) + dd;
         if (i1 < N) dE += 2.0f * dot3(de, bond(b0, b1, v)) + dd;
         dE = dE * kh + dw0;
-        acc0 = active && (d0.u < expf(-dE));
+        acc0 = active && (d0.u < __expf(-dE));
         if (acc0) b0 = n0;
     }
     // odd pass: bead 2p+1, neighbours 2p (this lane, updated) and 2p+2 (next lane)
@@ -487,7 +571,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
         float dE = 2.0f * dot3(de, bond(b1, b0, v)) + dd;
         if (i1 + 1 < N) dE += 2.0f * dot3(de, bond(b1, right, v)) + dd;
         dE = dE * kh + dw1;
-        acc1 = has1 && (d1.u < expf(-dE));
+        acc1 = has1 && (d1.u < __expf(-dE));
         if (acc1) b1 = n1;
     }
     if (active) store_pair(A, slot, b0, b1);
@@ -506,13 +590,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     }
 }
 
-// The sweep kernel: one launch per sweep for every system.  Each wave moves
-// one tile; every thread also folds (at most a few) count words of the
-// previous sweep, with the fold's loads issued before the move work and its
-// stores after it.
+// The sweep kernel: one launch per sweep for every system.  Wave w of the
+// grid moves the contiguous tile range [w T / W, (w+1) T / W) (T tiles, W
+// waves), loading the next tile's positions before moving the current one;
+// with W = T this is one tile per wave, with fewer waves each wave stays
+// resident and streams its range.  Every thread also folds count words of
+// the previous sweep (the first word's loads issued before the move work,
+// its stores after it).
 template <int R, int CW>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
+    using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
     const uint64_t s = *a.sweep_ctr + a.rel;
     const int64_t W = a.count_words;
     const CountView cin{a.base + ((s + 1) & 1) * W, a.delta + ((s + 2) % 3) * W};   // counts of sweep s
@@ -527,7 +615,18 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         fd = cin.delta[gtid];
     }
     const int wave = wave_tile(a.waves_per_block, a.xcd_remap);
-    if (wave < a.n_tiles) sweep_tile<R, CW>(a, wave, s, cin, dcur);
+    const int64_t n_waves = (int64_t)gridDim.x * a.waves_per_block;
+    const int t_begin = (int)((int64_t)a.n_tiles * wave / n_waves);
+    const int t_end = (int)((int64_t)a.n_tiles * (wave + 1) / n_waves);
+    Bead cb0, cb1;
+    if (t_begin < t_end) tile_load(a, t_begin, cb0, cb1);
+    for (int t = t_begin; t < t_end; ++t) {
+        Bead nb0, nb1;
+        if (t + 1 < t_end) tile_load(a, t + 1, nb0, nb1);
+        sweep_tile<R, CW>(a, t, s, cin, dcur, cb0, cb1);
+        cb0 = nb0;
+        cb1 = nb1;
+    }
     bool fold_ovf = false;
     if (gtid < W) {
         uint32_t w;
@@ -556,7 +655,7 @@ __global__ __launch_bounds__(256) void k_density(DensityArgs a)
     const SysView v = make_view(S);
     const int N = S.N, P = S.P;
     const int lane = (int)(threadIdx.x & 63);
-    const int g = lane / P;
+    const int g = (int)(((float)lane + 0.5f) * S.inv_P);
     const int p = lane - g * P;
     const int nin = min(S.G, S.n_chains - (int)T.chain0);
     const bool active = g < nin;
@@ -569,10 +668,11 @@ __global__ __launch_bounds__(256) void k_density(DensityArgs a)
     load_pair(A, slot, b0, b1);
     bool bad = false, ovf = false;
     const int c0 = cell_of(b0, v, bad);
-    ovf |= scatter_count<CW>(a.counts, S.cell_off + c0, pattern_type(S, chain, i0));
+    const int clog = (int)a.chain_id[S.chain_off + chain];
+    ovf |= scatter_count<CW>(a.counts, S.cell_off + c0, pattern_type(S, clog, i0));
     if (i1 < N) {
         const int c1 = cell_of(b1, v, bad);
-        ovf |= scatter_count<CW>(a.counts, S.cell_off + c1, pattern_type(S, chain, i1));
+        ovf |= scatter_count<CW>(a.counts, S.cell_off + c1, pattern_type(S, clog, i1));
     }
     if (ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
     if (bad) atomicOr(a.status, ST_CELL_OVERFLOW);
@@ -620,6 +720,153 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t n, uint32
 }
 
 __global__ void k_advance(uint64_t *ctr, uint32_t n) { *ctr += n; }
+
+// ---------------------------------------------------------------------------
+// Spatial chain reorder: chains are sorted by the cell of their first bead
+// (a counting sort over the context-wide cell index, which keeps every system
+// inside its own chain range), so that the waves of one XCD work on a compact
+// slab whose counts stay in that XCD's L2.  Logical chain ids move with the
+// chains, so the sweep's results do not change.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(256) void k_reorder_keys(ReorderArgs a)
+{
+    using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    if (wave >= a.n_tiles) return;
+    const Tile T = a.tiles[wave];
+    const DevSys &S = a.systems[T.sys];
+    const SysView v = make_view(S);
+    const int P = S.P;
+    const int lane = (int)(threadIdx.x & 63);
+    const int g = (int)(((float)lane + 0.5f) * S.inv_P);
+    const int p = lane - g * P;
+    const int nin = min(S.G, S.n_chains - (int)T.chain0);
+    if (g >= nin || p != 0) return;
+    const int chain = (int)T.chain0 + g;
+    const int64_t slot = S.slot_off + (int64_t)chain * (2 * P);
+    Bead b0, b1;
+    load_pair(PosArrays{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2}, slot, b0, b1);
+    bool bad = false;
+    const uint32_t key = (uint32_t)(S.cell_off + cell_of(b0, v, bad));
+    a.keys[S.chain_off + chain] = key;
+    atomicAdd(a.hist + key, 1u);
+}
+
+// Exclusive scan of hist[0, n) in place: block sums, a scan of the block
+// sums by one block, then the block-local scans plus offsets.
+constexpr int kScanBlock = 1024, kScanPer = 4, kScanTile = kScanBlock * kScanPer;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        const uint32_t x = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    total = sh[kScanBlock - 1];
+    const uint32_t incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_partials(const uint32_t *hist, int64_t n, uint32_t *bsum)
+{
+    __shared__ uint32_t sh[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    uint32_t v = 0;
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < n) v += hist[base + k];
+    uint32_t total;
+    (void)block_exclusive_scan(v, sh, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_bsum(uint32_t *bsum, int nb)
+{
+    __shared__ uint32_t sh[kScanBlock];
+    uint32_t carry = 0;
+    for (int start = 0; start < nb; start += kScanBlock) {
+        const int i = start + (int)threadIdx.x;
+        const uint32_t v = i < nb ? bsum[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan(v, sh, total);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(uint32_t *hist, int64_t n, const uint32_t *bsum)
+{
+    __shared__ uint32_t sh[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    uint32_t vals[kScanPer];
+    uint32_t v = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        vals[k] = base + k < n ? hist[base + k] : 0u;
+        v += vals[k];
+    }
+    uint32_t total;
+    uint32_t run = bsum[blockIdx.x] + block_exclusive_scan(v, sh, total);
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < n) {
+            hist[base + k] = run;
+            run += vals[k];
+        }
+}
+
+// perm[new] = old: each chain takes the next free place of its key.
+__global__ __launch_bounds__(256) void k_reorder_scatter(ReorderArgs a)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.total_chains) return;
+    const uint32_t pos = atomicAdd(a.hist + a.keys[c], 1u);
+    if (pos < (uint64_t)a.total_chains) a.perm[pos] = (uint32_t)c;
+    else atomicOr(a.status, ST_INTERNAL);
+}
+
+// Move chain perm[new] into place `new` (scratch copy), with its logical id.
+template <int R>
+__global__ __launch_bounds__(256) void k_reorder_permute(ReorderArgs a)
+{
+    using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    if (wave >= a.n_tiles) return;
+    const Tile T = a.tiles[wave];
+    const DevSys &S = a.systems[T.sys];
+    const int P = S.P;
+    const int lane = (int)(threadIdx.x & 63);
+    const int g = (int)(((float)lane + 0.5f) * S.inv_P);
+    const int p = lane - g * P;
+    const int nin = min(S.G, S.n_chains - (int)T.chain0);
+    if (g >= nin) return;
+    const int chain = (int)T.chain0 + g;
+    const int64_t old = (int64_t)a.perm[S.chain_off + chain] - S.chain_off;
+    if (old < 0 || old >= S.n_chains) {           // a chain left its system: never expected
+        atomicOr(a.status, ST_INTERNAL);
+        return;
+    }
+    Bead b0, b1;
+    load_pair(PosArrays{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2}, S.slot_off + old * (2 * P) + 2 * p, b0, b1);
+    store_pair(PosArrays{a.Q0, a.Q1, a.Q2, a.D0, a.D1, a.D2}, S.slot_off + (int64_t)chain * (2 * P) + 2 * p, b0, b1);
+    if (p == 0) a.chain_id2[S.chain_off + chain] = a.chain_id[S.chain_off + old];
+}
+
+// Logical chain ids in system order (identity within each system).
+__global__ __launch_bounds__(256) void k_iota_chains(ReorderArgs a)
+{
+    const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    if (wave >= a.n_tiles) return;
+    const Tile T = a.tiles[wave];
+    const DevSys &S = a.systems[T.sys];
+    const int lane = (int)(threadIdx.x & 63);
+    const int chain = (int)T.chain0 + lane;
+    if (lane < S.G && chain < S.n_chains) a.chain_id[S.chain_off + chain] = (uint32_t)chain;
+}
 
 // ---------------------------------------------------------------------------
 // Initial configuration: Gaussian random walks on the GPU (Sec. 2.2 moved
@@ -834,7 +1081,8 @@ static hipError_t launch_sweep_t(const SweepArgs &a, int blocks, hipStream_t st)
 
 hipError_t launch_sweep(int repr, int cw, const SweepArgs &a, hipStream_t st)
 {
-    const int blocks = (a.n_tiles + a.waves_per_block - 1) / a.waves_per_block;
+    int blocks = (a.n_tiles + a.waves_per_block - 1) / a.waves_per_block;
+    if (a.max_blocks > 0 && blocks > a.max_blocks) blocks = a.max_blocks;
     if (repr == REPR_F32)
         return cw == COUNT_U16 ? launch_sweep_t<REPR_F32, COUNT_U16>(a, blocks, st)
                                : launch_sweep_t<REPR_F32, COUNT_U32>(a, blocks, st);
@@ -890,6 +1138,35 @@ hipError_t launch_advance(uint64_t *ctr, uint32_t n, hipStream_t st)
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, st, ctr, n);
     return hipGetLastError();
 }
+
+hipError_t launch_iota_chains(const ReorderArgs &a, hipStream_t st)
+{
+    const int blocks = (a.n_tiles + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota_chains, dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reorder(int repr, const ReorderArgs &a, hipStream_t st)
+{
+    const int tblocks = (a.n_tiles + 3) / 4;
+    if (tblocks == 0) return hipSuccess;
+    hipError_t e = launch_fill_u32(a.hist, a.total_cells, 0u, st);
+    if (e != hipSuccess) return e;
+    if (repr == REPR_F32) hipLaunchKernelGGL((k_reorder_keys<REPR_F32>), dim3(tblocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_reorder_keys<REPR_CELL>), dim3(tblocks), dim3(256), 0, st, a);
+    const int nb = (int)((a.total_cells + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kScanBlock), 0, st, a.hist, a.total_cells, a.bsum);
+    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, st, a.bsum, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanBlock), 0, st, a.hist, a.total_cells, a.bsum);
+    const int cblocks = (int)((a.total_chains + 255) / 256);
+    hipLaunchKernelGGL(k_reorder_scatter, dim3(cblocks), dim3(256), 0, st, a);
+    if (repr == REPR_F32) hipLaunchKernelGGL((k_reorder_permute<REPR_F32>), dim3(tblocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_reorder_permute<REPR_CELL>), dim3(tblocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+int64_t reorder_bsum_words(int64_t total_cells) { return (total_cells + kScanTile - 1) / kScanTile; }
 
 hipError_t launch_init(const InitArgs &a, hipStream_t st)
 {

@@ -12,8 +12,9 @@ struct SweepArgs {
     const Tile *tiles;
     int n_tiles;
     int waves_per_block;
+    int max_blocks;                // 0: one tile per wave; else the grid size (waves loop over tiles)
     int xcd_remap;
-    const uint32_t *chain_id;      // logical chain id per chain slot, or null for identity
+    const uint32_t *chain_id;      // logical chain id (within its system) per chain slot
     float *P0, *P1, *P2;           // coordinates (F32) or offsets (CELL)
     int *C0, *C1, *C2;             // cells (CELL only)
     uint32_t *base;                // two rotating base-count buffers
@@ -30,10 +31,28 @@ struct SweepArgs {
 struct DensityArgs {
     const DevSys *systems;
     const Tile *tiles;
+    const uint32_t *chain_id;
     int tile_begin, tile_end;
     float *P0, *P1, *P2;
     int *C0, *C1, *C2;
     uint32_t *counts;              // the target buffer (zeroed by the caller)
+    uint32_t *status;
+};
+
+struct ReorderArgs {
+    const DevSys *systems;
+    const Tile *tiles;
+    int n_tiles;
+    int64_t total_chains, total_cells;
+    float *P0, *P1, *P2;           // live positions
+    int *C0, *C1, *C2;
+    float *Q0, *Q1, *Q2;           // scratch positions (same layout)
+    int *D0, *D1, *D2;
+    uint32_t *chain_id, *chain_id2;
+    uint32_t *keys;                // per chain: context-wide cell of bead 0
+    uint32_t *hist;                // per cell: count, then exclusive offsets
+    uint32_t *bsum;                // scan block sums
+    uint32_t *perm;                // perm[new] = old
     uint32_t *status;
 };
 
@@ -84,6 +103,9 @@ hipError_t launch_unpack_counts(int cw, const uint32_t *base, const uint32_t *de
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_advance(uint64_t *ctr, uint32_t n, hipStream_t st);
 hipError_t launch_init(const InitArgs &a, hipStream_t st);
+hipError_t launch_iota_chains(const ReorderArgs &a, hipStream_t st);
+hipError_t launch_reorder(int repr, const ReorderArgs &a, hipStream_t st);
+int64_t reorder_bsum_words(int64_t total_cells);
 hipError_t launch_observables(int cw, const ObsArgs &a, double *out, hipStream_t st);
 
 }  // namespace soma

@@ -23,6 +23,7 @@ enum StatusBits : uint32_t {
     ST_COUNT_OVERFLOW = 1u,
     ST_NONFINITE = 2u,
     ST_CELL_OVERFLOW = 4u,
+    ST_INTERNAL = 8u,
 };
 
 // One system, as the kernels see it.  Offsets are in elements of the flat
@@ -44,6 +45,7 @@ struct alignas(16) DevSys {
     float inv_edge[3];     // 1 / edge (FP32)
     float k_half;          // k/2 = 3(N-1)/(2 Re^2)
     float delta;           // move half-width
+    float inv_P;           // 1 / P
     // omega_A = cAA nA + cAB nB + c0, omega_B = cBA nA + cBB nB + c0
     float cAA, cAB, cBA, cBB, c0;
     int64_t n_cells;

@@ -113,10 +113,11 @@ def test_fields_match_oracle(name):
     g.close()
 
 
+@pytest.mark.parametrize("reorder", [0, 1])
 @pytest.mark.parametrize("name", list(small_cases()))
-def test_single_and_multi_sweep_parity(name):
+def test_single_and_multi_sweep_parity(name, reorder):
     systems, r, cw = small_cases()[name]
-    g, orcs = make_pair(systems, r, cw)
+    g, orcs = make_pair(systems, r, cw, reorder_every=reorder)
     total, mism = 0, 0
     for sweep in range(3):
         g.sweep(1)
@@ -187,15 +188,18 @@ def test_gpu_init_matches_oracle_walks(r):
 def test_graph_tiling_and_xcd_invariance():
     systems = W.batched_mixed(n_systems=6, seed=46, bead_range=(2000, 15000))
     ref = None
-    for use_graph, wpb in [(False, 1), (True, 4), (True, 16), (False, 7)]:
-        g = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, use_graph=use_graph, waves_per_block=wpb)
+    for use_graph, wpb, wpcu, reorder in [(False, 1, 0, 0), (True, 4, 0, 0), (True, 16, 0, 0), (False, 7, 0, 0),
+                                          (True, 4, 1, 0), (True, 2, 8, 0), (True, 4, 0, 1), (False, 4, 0, 2),
+                                          (True, 4, 0, 3)]:
+        g = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, use_graph=use_graph, waves_per_block=wpb,
+                 waves_per_cu=wpcu, reorder_every=reorder)
         g.sweep(5)
         st = [g.state(k) for k in range(len(systems))]
         if ref is None:
             ref = st
         else:
             for a, b in zip(ref, st):
-                assert (a[0] == b[0]).all() and (a[1] == b[1]).all(), (use_graph, wpb)
+                assert (a[0] == b[0]).all() and (a[1] == b[1]).all(), (use_graph, wpb, wpcu, reorder)
         g.close()
 
 
