@@ -73,7 +73,7 @@ def run_workload(name, steps, warmup, wpb=0):
     systems = W.workload(name)
     o = W.WORKLOAD_OPTIONS[name]
     g = Soma(systems, seed=SEED, pos_repr=o["pos_repr"], count_width=o["count_width"],
-             use_graph=True, waves_per_block=wpb)
+             use_graph=True, waves_per_block=wpb, reorder_every=o["reorder_every"])
     info = g.info()
     sec, wall = timed_sweeps(g, steps, warmup)
     obs = g.observables(0)
@@ -89,7 +89,8 @@ def batched_vs_plain(steps, warmup):
     systems = W.batched_uneven()
     o = W.WORKLOAD_OPTIONS["batched_uneven"]
     B = sum(s.n_beads for s in systems)
-    g = Soma(systems, seed=SEED, pos_repr=o["pos_repr"], count_width=o["count_width"], use_graph=True)
+    g = Soma(systems, seed=SEED, pos_repr=o["pos_repr"], count_width=o["count_width"], use_graph=True,
+             reorder_every=o["reorder_every"])
     sec_b, _ = timed_sweeps(g, steps, warmup)
     info_b = g.info()
     re2_b = [g.observables(k)["Re2"] for k in range(len(systems))]
@@ -98,7 +99,7 @@ def batched_vs_plain(steps, warmup):
     re2_p = []
     for k, s in enumerate(systems):
         a = Soma([s], seed=SEED, pos_repr=o["pos_repr"], count_width=o["count_width"], use_graph=True,
-                 sys_id_base=k)
+                 sys_id_base=k, reorder_every=o["reorder_every"])
         t, _ = timed_sweeps(a, steps, warmup)
         sec_p += t
         re2_p.append(a.observables(0)["Re2"])
@@ -114,6 +115,20 @@ def batched_vs_plain(steps, warmup):
         "batched_hbm_gbs": info_b["bytes_per_sweep"] * steps / sec_b / 1e9,
         "re2_max_abs_diff_batched_vs_plain": float(np.abs(re2_b - re2_p).max()),
     }
+
+
+def measured_traffic(workload):
+    """HBM bytes per k_sweep launch from the committed rocprofv3 counter summary,
+    only while the kernel source is the one that was profiled (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_traffic.json")
+    src = os.path.join(ROOT, "paper_2606_09356_amd", "csrc", "soma_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(name, budget_s=15.0):
@@ -178,7 +193,7 @@ def main():
                                "Gaussian-walk start, delta 0.05 Re, 128 beads/Re^3, cell Re/4",
                    "beads": B, "sweeps_per_step": 1, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "bytes_per_sweep": info["bytes_per_sweep"],
                      "kernel": "k_sweep (move + density + field, one launch per sweep)",
                      "avg_sweep_us_hip_events": sec / args.steps * 1e6},
@@ -196,6 +211,16 @@ def main():
                               "hbm_gbs": minfo["bytes_per_sweep"] * mst / msec / 1e9,
                               "frac": minfo["bytes_per_sweep"] * mst / msec / 1e9 / HBM_PEAK_GBS,
                               "beads": minfo["n_beads"], "Re2": mobs["Re2"]}
+        print("[bench] batched mixed-precision workload", flush=True)
+        bs, binfo, bsec, _, _ = run_workload("batched_mixed", min(args.steps, 100), min(args.warmup, 10))
+        bst = min(args.steps, 100)
+        out["batched_mixed"] = {"workload": "256 systems of A/B blends, AB and ABA (N 8..128, 1e4..1e6 beads), "
+                                            "int32 cell + FP32 offset, uint16 counts",
+                                "moves_per_s": binfo["n_beads"] * bst / bsec,
+                                "hbm_gbs": binfo["bytes_per_sweep"] * bst / bsec / 1e9,
+                                "frac": binfo["bytes_per_sweep"] * bst / bsec / 1e9 / HBM_PEAK_GBS,
+                                "beads": binfo["n_beads"], "systems": len(bs),
+                                "over_plain_large": (binfo["n_beads"] * bst / bsec) / moves_per_s}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)

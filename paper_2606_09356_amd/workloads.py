@@ -171,11 +171,11 @@ def workload(name: str, **kw) -> List[SystemDesc]:
 
 # Options per workload: position representation and count width.
 WORKLOAD_OPTIONS = {
-    "plain_small": dict(pos_repr="f32", count_width=16, sweeps=1000),
-    "plain_large": dict(pos_repr="f32", count_width=16, sweeps=200),
-    "mixed_large": dict(pos_repr="cell", count_width=32, sweeps=100),
-    "batched_uneven": dict(pos_repr="f32", count_width=16, sweeps=500),
-    "batched_mixed": dict(pos_repr="cell", count_width=16, sweeps=200),
+    "plain_small": dict(pos_repr="f32", count_width=16, sweeps=1000, reorder_every=100),
+    "plain_large": dict(pos_repr="f32", count_width=16, sweeps=200, reorder_every=100),
+    "mixed_large": dict(pos_repr="cell", count_width=32, sweeps=100, reorder_every=100),
+    "batched_uneven": dict(pos_repr="f32", count_width=16, sweeps=500, reorder_every=100),
+    "batched_mixed": dict(pos_repr="cell", count_width=16, sweeps=200, reorder_every=100),
 }
 
 
