@@ -27,7 +27,7 @@ thread_local std::string g_create_error;
 
 struct Layout {
     size_t systems, tiles, chain_id, chain_id2, P[3], C[3], Q[3], D[3], keys, hist, bsum, perm, base, delta,
-        omega, accept, status, partials, obs_out, staging, total;
+        omega, accept, status, partials, obs_out, staging, total;   // base: counts, delta: density delta
     int64_t total_slots = 0, total_cells = 0, total_chains = 0, count_words = 0;
     int n_tiles = 0;
     int64_t max_obs_blocks = 0, max_cells = 0;
@@ -69,11 +69,9 @@ struct soma_ctx {
     int *D(int d) const { return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + L.D[d]) : nullptr; }
     uint32_t *chain_id() const { return reinterpret_cast<uint32_t *>(ws + L.chain_id); }
     uint32_t *u32(size_t off) const { return reinterpret_cast<uint32_t *>(ws + off); }
-    // Counts after S sweeps are base[(S-1) mod 2] + delta[(S-1) mod 3].
-    uint32_t *base() const { return reinterpret_cast<uint32_t *>(ws + L.base); }
+    // Current counts; the density delta of a sweep is folded in right after it.
+    uint32_t *counts() const { return reinterpret_cast<uint32_t *>(ws + L.base); }
     uint32_t *delta() const { return reinterpret_cast<uint32_t *>(ws + L.delta); }
-    uint32_t *cur_base(uint64_t S) const { return base() + ((S + 1) % 2) * L.count_words; }
-    uint32_t *cur_delta(uint64_t S) const { return delta() + ((S + 2) % 3) * L.count_words; }
     float2 *omega() const { return reinterpret_cast<float2 *>(ws + L.omega); }
     unsigned long long *accept() const { return reinterpret_cast<unsigned long long *>(ws + L.accept); }
     uint32_t *status() const { return reinterpret_cast<uint32_t *>(ws + L.status); }
@@ -243,8 +241,8 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     L.hist = take(sizeof(uint32_t) * cells);
     L.bsum = take(sizeof(uint32_t) * soma::reorder_bsum_words(cells));
     L.perm = take(sizeof(uint32_t) * chains);
-    L.base = take(sizeof(uint32_t) * 2 * L.count_words);
-    L.delta = take(sizeof(uint32_t) * 3 * L.count_words);
+    L.base = take(sizeof(uint32_t) * L.count_words);
+    L.delta = take(sizeof(uint32_t) * L.count_words);
     L.omega = take(sizeof(float) * 2 * cells);
     L.accept = take(sizeof(uint64_t) * soma::kAcceptSlots * soma::kAcceptStride * n_sys);
     L.status = take(64);
@@ -295,7 +293,7 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
         (&a.P0)[d] = c->P(d);
         (&a.C0)[d] = c->C(d);
     }
-    a.base = c->base();
+    a.counts = c->counts();
     a.delta = c->delta();
     a.count_words = c->L.count_words;
     a.omega = c->omega();
@@ -311,8 +309,8 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
 // base counts with a zero delta.
 int rebuild_density(soma_ctx *c, int32_t sys)
 {
-    uint32_t *cur = c->cur_base(c->sweep);
-    uint32_t *dcur = c->cur_delta(c->sweep);
+    uint32_t *cur = c->counts();
+    uint32_t *dcur = c->delta();
     const int64_t wpc = c->words_per_cell();
     int tb = 0, te = c->L.n_tiles;
     if (sys < 0) {
@@ -394,6 +392,7 @@ int record_sweeps(soma_ctx *c, int32_t n, hipStream_t st)
     for (int32_t r = 0; r < n; ++r) {
         soma::SweepArgs a = sweep_args(c, (uint32_t)r);
         HIPCHK(c, soma::launch_sweep(c->repr, c->cw, a, st));
+        HIPCHK(c, soma::launch_fold(c->cw, c->counts(), c->delta(), c->L.count_words, c->status(), st));
     }
     HIPCHK(c, soma::launch_advance(c->sweep_ctr(), (uint32_t)n, st));
     return SOMA_OK;
@@ -570,8 +569,8 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
         return bail(hip_fail(c, e, "upload tiles"));
     // clear counts, fields, accept counters, status and sweep counter
     if ((rc = [&] {
-             HIPCHK(c, soma::launch_fill_u32(c->base(), 2 * c->L.count_words, 0u, c->stream));
-             HIPCHK(c, soma::launch_fill_u32(c->delta(), 3 * c->L.count_words, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(c->counts(), c->L.count_words, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(c->delta(), c->L.count_words, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->omega()), 2 * c->L.total_cells, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->accept()),
                                              2 * (int64_t)soma::kAcceptSlots * soma::kAcceptStride * n_sys, 0u, c->stream));
@@ -660,8 +659,7 @@ int soma_density(soma_ctx *c, int32_t sys, uint32_t *dst, int32_t dst_on_device)
     if (!dst) return fail(c, SOMA_EINVAL, "dst is null");
     const HostSys &h = c->sys[sys];
     uint32_t *target = dst_on_device ? dst : static_cast<uint32_t *>(c->staging());
-    HIPCHK(c, soma::launch_unpack_counts(c->cw, c->cur_base(c->sweep), c->cur_delta(c->sweep), h.dev.cell_off,
-                                         h.dev.n_cells, target, c->stream));
+    HIPCHK(c, soma::launch_unpack_counts(c->cw, c->counts(), h.dev.cell_off, h.dev.n_cells, target, c->stream));
     if (!dst_on_device)
         HIPCHK(c, hipMemcpyAsync(dst, target, sizeof(uint32_t) * 2 * h.dev.n_cells, hipMemcpyDeviceToHost, c->stream));
     return sync_status(c);
@@ -678,8 +676,7 @@ int soma_fields(soma_ctx *c, int32_t sys, float *dst, int32_t dst_on_device)
     f.systems = c->d_sys();
     f.sys = sys;
     f.n_cells = h.dev.n_cells;
-    f.base = c->cur_base(c->sweep);
-    f.delta = c->cur_delta(c->sweep);
+    f.counts = c->counts();
     f.omega = c->omega();
     f.out = dst_on_device ? dst : static_cast<float *>(c->staging());
     HIPCHK(c, soma::launch_fields(c->cw, f, c->stream));
@@ -707,8 +704,7 @@ int soma_observables(soma_ctx *c, int32_t sys, soma_obs *out)
         (&a.C0)[d] = c->C(d);
     }
     a.k_half = 1.5 * (h.d.N - 1) / (h.d.Re * h.d.Re);
-    a.base = c->cur_base(c->sweep);
-    a.delta = c->cur_delta(c->sweep);
+    a.counts = c->counts();
     a.cell_off = h.dev.cell_off;
     a.n_cells = h.dev.n_cells;
     const double B = (double)h.d.n_chains * h.d.N;
@@ -877,8 +873,7 @@ int soma_set_sweep(soma_ctx *c, uint64_t sweep)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->sweep_ctr(), &sweep, sizeof sweep, hipMemcpyHostToDevice));
     c->sweep = sweep;
-    HIPCHK(c, soma::launch_fill_u32(c->base(), 2 * c->L.count_words, 0u, c->stream));
-    HIPCHK(c, soma::launch_fill_u32(c->delta(), 3 * c->L.count_words, 0u, c->stream));
+    HIPCHK(c, soma::launch_fill_u32(c->delta(), c->L.count_words, 0u, c->stream));
     if ((rc = rebuild_density(c, -1)) != SOMA_OK) return rc;
     return sync_status(c);
 }
@@ -896,8 +891,8 @@ int soma_get_info(soma_ctx *c, soma_info *out)
     out->n_beads = beads;
     out->n_cells = cells;
     out->sweep = c->sweep;
-    // positions read + write; fold of the counts: base and delta read, base
-    // written, next delta cleared (the field gathers hit these same lines)
+    // positions read + write; fold of the counts: counts and delta read,
+    // counts written, delta cleared (the field gathers hit these same lines)
     const int64_t pos = c->repr == soma::REPR_F32 ? 12 : 24;
     const int64_t cnt = c->cw == soma::COUNT_U16 ? 4 : 8;
     out->bytes_per_sweep = 2 * pos * beads + 4 * cnt * cells;

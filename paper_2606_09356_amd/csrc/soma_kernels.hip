@@ -17,13 +17,11 @@
 //   * The fields are never stored: omega of a cell is an affine function of
 //     its two counts, evaluated where a moved bead needs it (only when the
 //     trial move leaves the bead's cell).
-//   * The density is kept as base counts plus a delta: a sweep adds -1/+1
-//     atomically only for accepted moves that change cell (about 0.2 of the
-//     beads), not one atomic per bead.  The counts of sweep s are
-//     B[s-1] + D[s-1]; sweep s reads them (fields), atomically accumulates
-//     its own changes in D[s], writes B[s] = B[s-1] + D[s-1] and clears
-//     D[s+1] -- two base and three delta buffers in rotation, so move,
-//     density and field refresh are one launch per sweep.
+//   * The density is updated, not rebuilt: a sweep reads the counts C
+//     (frozen, for the fields) and adds -1/+1 atomically to a delta D only
+//     for accepted moves that change cell (about 0.2 of the beads), not one
+//     atomic per bead.  A short streaming kernel then folds C += D, D = 0;
+//     the fields of the next sweep follow from the folded counts.
 //   * Philox4x32-10 is counter based: one 128-bit block per (bead, logical
 //     chain, sweep, system); no RNG state lives in memory.
 #include <hip/hip_runtime.h>
@@ -295,56 +293,39 @@ __device__ __forceinline__ void store_pair(const PosArrays &A, int64_t slot, con
 // ---------------------------------------------------------------------------
 // U16: one uint32 per cell, A in the low half, B in the high half.
 // U32: two uint32 per cell (A, B) interleaved.
-// Counts are base + delta in modular uint32 arithmetic: for U16 the packed
-// sum equals nA + 2^16 nB exactly whenever both true counts fit 16 bits.
-struct CountView {
-    const uint32_t *base;
-    const uint32_t *delta;
-};
-
 template <int CW>
-__device__ __forceinline__ uint2 load_counts(const CountView &v, int64_t cell)
+__device__ __forceinline__ uint2 load_counts(const uint32_t *cnt, int64_t cell)
 {
     if constexpr (CW == COUNT_U16) {
-        const uint32_t w = v.base[cell] + v.delta[cell];
+        const uint32_t w = cnt[cell];
         return make_uint2(w & 0xFFFFu, w >> 16);
     } else {
-        const uint2 b = *reinterpret_cast<const uint2 *>(v.base + 2 * cell);
-        const uint2 d = *reinterpret_cast<const uint2 *>(v.delta + 2 * cell);
-        return make_uint2(b.x + d.x, b.y + d.y);
+        return *reinterpret_cast<const uint2 *>(cnt + 2 * cell);
     }
 }
 
-// Raw base and delta words of one cell, loaded without being combined so that
-// several gathers can be in flight before the first use.
+// Raw count words of one cell, loaded without being unpacked so that several
+// gathers can be in flight before the first use.
 struct RawCount {
-    uint32_t b0, d0, b1, d1;
+    uint32_t w0, w1;
 };
 
 template <int CW>
-__device__ __forceinline__ RawCount load_raw(const CountView &v, int64_t cell)
+__device__ __forceinline__ RawCount load_raw(const uint32_t *cnt, int64_t cell)
 {
-    RawCount r{0u, 0u, 0u, 0u};
     if constexpr (CW == COUNT_U16) {
-        r.b0 = v.base[cell];
-        r.d0 = v.delta[cell];
+        return RawCount{cnt[cell], 0u};
     } else {
-        const uint2 b = *reinterpret_cast<const uint2 *>(v.base + 2 * cell);
-        const uint2 d = *reinterpret_cast<const uint2 *>(v.delta + 2 * cell);
-        r.b0 = b.x; r.b1 = b.y; r.d0 = d.x; r.d1 = d.y;
+        const uint2 w = *reinterpret_cast<const uint2 *>(cnt + 2 * cell);
+        return RawCount{w.x, w.y};
     }
-    return r;
 }
 
 template <int CW>
 __device__ __forceinline__ uint2 counts_of(const RawCount &r)
 {
-    if constexpr (CW == COUNT_U16) {
-        const uint32_t w = r.b0 + r.d0;
-        return make_uint2(w & 0xFFFFu, w >> 16);
-    } else {
-        return make_uint2(r.b0 + r.d0, r.b1 + r.d1);
-    }
+    if constexpr (CW == COUNT_U16) return make_uint2(r.w0 & 0xFFFFu, r.w0 >> 16);
+    else return make_uint2(r.w0, r.w1);
 }
 
 // One bead of type t leaves cell `from` and enters cell `to` (non-returning
@@ -362,8 +343,10 @@ __device__ __forceinline__ void move_count(uint32_t *delta, int64_t from, int64_
     }
 }
 
-// Fold one word: base' = base + delta; returns true if a true count left its
-// range (below zero, or above 65535 for packed 16-bit counts).
+// Fold one word: counts' = counts + delta in modular uint32 arithmetic (for
+// U16 the packed sum is exact whenever both true counts fit 16 bits); returns
+// true if a true count left its range (below zero, or above 65535 for packed
+// 16-bit counts).
 template <int CW>
 __device__ __forceinline__ bool fold_word(uint32_t b, uint32_t d, uint32_t &out)
 {
@@ -404,7 +387,7 @@ __device__ __forceinline__ float omega_of(const FieldCoef &f, uint2 n, int t)
 }
 
 template <int CW>
-__device__ __forceinline__ float omega_at(bool frozen, const float2 *omega, const CountView &cnt,
+__device__ __forceinline__ float omega_at(bool frozen, const float2 *omega, const uint32_t *cnt,
                                           int64_t cell_off, int cell, int t, const FieldCoef &f)
 {
     if (frozen) {
@@ -485,7 +468,7 @@ __device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0
 // One wave tile of the sweep: the even pass, the odd pass and the density
 // delta of up to G whole chains, from positions already loaded by tile_load.
 template <int R, int CW, class Bead>
-__device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const CountView &cin,
+__device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                            uint32_t *dcur, Bead b0, Bead b1)
 {
     const Tile T = a.tiles[wave];
@@ -541,7 +524,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
         dw0 = t0 ? wn0.y - wo0.y : wn0.x - wo0.x;
         dw1 = t1 ? wn1.y - wo1.y : wn1.x - wo1.x;
     } else {
-        RawCount rn0{0u, 0u, 0u, 0u}, ro0{0u, 0u, 0u, 0u}, rn1{0u, 0u, 0u, 0u}, ro1{0u, 0u, 0u, 0u};
+        RawCount rn0{0u, 0u}, ro0{0u, 0u}, rn1{0u, 0u}, ro1{0u, 0u};
         if (g0) { rn0 = load_raw<CW>(cin, cell_off + nc0); ro0 = load_raw<CW>(cin, cell_off + old0); }
         if (g1) { rn1 = load_raw<CW>(cin, cell_off + nc1); ro1 = load_raw<CW>(cin, cell_off + old1); }
         if (g0) dw0 = omega_of(fc, counts_of<CW>(rn0), t0) - omega_of(fc, counts_of<CW>(ro0), t0);
@@ -592,55 +575,46 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
 
 // The sweep kernel: one launch per sweep for every system.  Wave w of the
 // grid moves the contiguous tile range [w T / W, (w+1) T / W) (T tiles, W
-// waves), loading the next tile's positions before moving the current one;
-// with W = T this is one tile per wave, with fewer waves each wave stays
-// resident and streams its range.  Every thread also folds count words of
-// the previous sweep (the first word's loads issued before the move work,
-// its stores after it).
-template <int R, int CW>
+// waves): with W = T (the default) one tile per wave; with fewer waves each
+// wave stays resident and walks its range.  One tile's state is live at a
+// time, which keeps the register count (and so the occupancy) of the
+// one-tile case.
+template <int R, int CW, bool LOOP>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
     const uint64_t s = *a.sweep_ctr + a.rel;
-    const int64_t W = a.count_words;
-    const CountView cin{a.base + ((s + 1) & 1) * W, a.delta + ((s + 2) % 3) * W};   // counts of sweep s
-    uint32_t *bcur = a.base + (s & 1) * W;
-    uint32_t *dcur = a.delta + (s % 3) * W;
-    uint32_t *dnext = a.delta + ((s + 1) % 3) * W;
-    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    uint32_t fb = 0u, fd = 0u;
-    if (gtid < W) {
-        fb = cin.base[gtid];
-        fd = cin.delta[gtid];
-    }
     const int wave = wave_tile(a.waves_per_block, a.xcd_remap);
-    const int64_t n_waves = (int64_t)gridDim.x * a.waves_per_block;
-    const int t_begin = (int)((int64_t)a.n_tiles * wave / n_waves);
-    const int t_end = (int)((int64_t)a.n_tiles * (wave + 1) / n_waves);
-    Bead cb0, cb1;
-    if (t_begin < t_end) tile_load(a, t_begin, cb0, cb1);
-    for (int t = t_begin; t < t_end; ++t) {
-        Bead nb0, nb1;
-        if (t + 1 < t_end) tile_load(a, t + 1, nb0, nb1);
-        sweep_tile<R, CW>(a, t, s, cin, dcur, cb0, cb1);
-        cb0 = nb0;
-        cb1 = nb1;
+    if constexpr (LOOP) {
+        const int64_t n_waves = (int64_t)gridDim.x * a.waves_per_block;
+        const int t_begin = (int)((int64_t)a.n_tiles * wave / n_waves);
+        const int t_end = (int)((int64_t)a.n_tiles * (wave + 1) / n_waves);
+        for (int t = t_begin; t < t_end; ++t) {
+            Bead b0, b1;
+            tile_load(a, t, b0, b1);
+            sweep_tile<R, CW>(a, t, s, a.counts, a.delta, b0, b1);
+        }
+    } else {
+        if (wave >= a.n_tiles) return;
+        Bead b0, b1;
+        tile_load(a, wave, b0, b1);
+        sweep_tile<R, CW>(a, wave, s, a.counts, a.delta, b0, b1);
     }
-    bool fold_ovf = false;
-    if (gtid < W) {
+}
+
+// Fold the sweep's density delta into the counts and clear it.
+template <int CW>
+__global__ __launch_bounds__(256) void k_fold(uint32_t *counts, uint32_t *delta, int64_t n, uint32_t *status)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool ovf = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         uint32_t w;
-        fold_ovf |= fold_word<CW>(fb, fd, w);
-        bcur[gtid] = w;
-        dnext[gtid] = 0u;
+        ovf |= fold_word<CW>(counts[i], delta[i], w);
+        counts[i] = w;
+        delta[i] = 0u;
     }
-    for (int64_t i = gtid + nthreads; i < W; i += nthreads) {
-        uint32_t w;
-        fold_ovf |= fold_word<CW>(cin.base[i], cin.delta[i], w);
-        bcur[i] = w;
-        dnext[i] = 0u;
-    }
-    if (fold_ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
+    if (ovf) atomicOr(status, ST_COUNT_OVERFLOW);
 }
 
 template <int R, int CW>
@@ -693,7 +667,7 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs a)
         wb = w.y;
     } else {
         const FieldCoef fc{S.cAA, S.cAB, S.cBA, S.cBB, S.c0};
-        const uint2 n = load_counts<CW>(CountView{a.base, a.delta}, S.cell_off + c);
+        const uint2 n = load_counts<CW>(a.counts, S.cell_off + c);
         wa = omega_of(fc, n, 0);
         wb = omega_of(fc, n, 1);
     }
@@ -703,12 +677,12 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs a)
 
 // Counts of one system as uint32 [2][M].
 template <int CW>
-__global__ __launch_bounds__(256) void k_unpack_counts(const uint32_t *base, const uint32_t *delta,
-                                                       int64_t cell_off, int64_t n_cells, uint32_t *out)
+__global__ __launch_bounds__(256) void k_unpack_counts(const uint32_t *counts, int64_t cell_off, int64_t n_cells,
+                                                       uint32_t *out)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
-    const uint2 n = load_counts<CW>(CountView{base, delta}, cell_off + c);
+    const uint2 n = load_counts<CW>(counts, cell_off + c);
     out[c] = n.x;
     out[n_cells + c] = n.y;
 }
@@ -1031,7 +1005,7 @@ __global__ __launch_bounds__(256) void k_obs_cells(ObsArgs a)
     for (int k = 0; k < kObsQ; ++k) q[k] = NSum{0.0, 0.0};
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c < a.n_cells) {
-        const uint2 n = load_counts<CW>(CountView{a.base, a.delta}, a.cell_off + c);
+        const uint2 n = load_counts<CW>(a.counts, a.cell_off + c);
         const double pa = (double)n.x * a.phi_per_count, pb = (double)n.y * a.phi_per_count;
         const double inc = pa + pb - 1.0;
         double f;
@@ -1075,7 +1049,10 @@ __global__ __launch_bounds__(256) void k_obs_finalize(const double *partials, in
 template <int R, int CW>
 static hipError_t launch_sweep_t(const SweepArgs &a, int blocks, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_sweep<R, CW>), dim3(blocks), dim3(64 * a.waves_per_block), 0, st, a);
+    if (a.max_blocks > 0)
+        hipLaunchKernelGGL((k_sweep<R, CW, true>), dim3(blocks), dim3(64 * a.waves_per_block), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_sweep<R, CW, false>), dim3(blocks), dim3(64 * a.waves_per_block), 0, st, a);
     return hipGetLastError();
 }
 
@@ -1114,13 +1091,23 @@ hipError_t launch_fields(int cw, const FieldArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_unpack_counts(int cw, const uint32_t *base, const uint32_t *delta, int64_t cell_off,
-                                int64_t n_cells, uint32_t *out, hipStream_t st)
+hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off, int64_t n_cells,
+                                uint32_t *out, hipStream_t st)
 {
     const int blocks = (int)((n_cells + 255) / 256);
     if (blocks == 0) return hipSuccess;
-    if (cw == COUNT_U16) hipLaunchKernelGGL((k_unpack_counts<COUNT_U16>), dim3(blocks), dim3(256), 0, st, base, delta, cell_off, n_cells, out);
-    else hipLaunchKernelGGL((k_unpack_counts<COUNT_U32>), dim3(blocks), dim3(256), 0, st, base, delta, cell_off, n_cells, out);
+    if (cw == COUNT_U16) hipLaunchKernelGGL((k_unpack_counts<COUNT_U16>), dim3(blocks), dim3(256), 0, st, counts, cell_off, n_cells, out);
+    else hipLaunchKernelGGL((k_unpack_counts<COUNT_U32>), dim3(blocks), dim3(256), 0, st, counts, cell_off, n_cells, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(int cw, uint32_t *counts, uint32_t *delta, int64_t n, uint32_t *status, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (cw == COUNT_U16) hipLaunchKernelGGL((k_fold<COUNT_U16>), dim3((unsigned)blocks), dim3(256), 0, st, counts, delta, n, status);
+    else hipLaunchKernelGGL((k_fold<COUNT_U32>), dim3((unsigned)blocks), dim3(256), 0, st, counts, delta, n, status);
     return hipGetLastError();
 }
 

@@ -17,8 +17,8 @@ struct SweepArgs {
     const uint32_t *chain_id;      // logical chain id (within its system) per chain slot
     float *P0, *P1, *P2;           // coordinates (F32) or offsets (CELL)
     int *C0, *C1, *C2;             // cells (CELL only)
-    uint32_t *base;                // two rotating base-count buffers
-    uint32_t *delta;               // three rotating delta-count buffers
+    const uint32_t *counts;        // counts of this sweep (read only)
+    uint32_t *delta;               // density delta of this sweep (atomics)
     int64_t count_words;           // uint32 words per buffer
     const float2 *omega;           // frozen fields, per cell (A, B)
     const uint64_t *sweep_ctr;     // sweeps done before this graph / launch sequence
@@ -60,7 +60,7 @@ struct FieldArgs {
     const DevSys *systems;
     int sys;
     int64_t n_cells;
-    const uint32_t *base, *delta;  // current counts = base + delta
+    const uint32_t *counts;        // current counts
     const float2 *omega;
     float *out;                    // [2][n_cells]
 };
@@ -86,7 +86,7 @@ struct ObsArgs {
     double k_half;
     const float *P0, *P1, *P2;
     const int *C0, *C1, *C2;
-    const uint32_t *base, *delta;  // current counts = base + delta
+    const uint32_t *counts;        // current counts
     int64_t cell_off, n_cells;
     double phi_per_count;          // M / B
     double chiN, kappaN;
@@ -98,8 +98,9 @@ struct ObsArgs {
 hipError_t launch_sweep(int repr, int cw, const SweepArgs &a, hipStream_t st);
 hipError_t launch_density(int repr, int cw, const DensityArgs &a, hipStream_t st);
 hipError_t launch_fields(int cw, const FieldArgs &a, hipStream_t st);
-hipError_t launch_unpack_counts(int cw, const uint32_t *base, const uint32_t *delta, int64_t cell_off,
-                                int64_t n_cells, uint32_t *out, hipStream_t st);
+hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off, int64_t n_cells,
+                                uint32_t *out, hipStream_t st);
+hipError_t launch_fold(int cw, uint32_t *counts, uint32_t *delta, int64_t n, uint32_t *status, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_advance(uint64_t *ctr, uint32_t n, hipStream_t st);
 hipError_t launch_init(const InitArgs &a, hipStream_t st);
