@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one 1 GiB device copy (reference for HBM byte counters) and exit")
     p.add_argument("--waves-per-block", type=int, default=0)
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the default launch shape instead of timing every shape first")
     return p.parse_args()
 
 
@@ -67,21 +69,28 @@ def timed_sweeps(g, steps, warmup):
     return start.elapsed_time(end) / 1e3, wall
 
 
-def run_workload(name, steps, warmup, wpb=0):
+def run_workload(name, steps, warmup, wpb=0, autotune=True):
     from paper_2606_09356_amd import workloads as W
     from paper_2606_09356_amd.soma import Soma
     systems = W.workload(name)
     o = W.WORKLOAD_OPTIONS[name]
     g = Soma(systems, seed=SEED, pos_repr=o["pos_repr"], count_width=o["count_width"],
              use_graph=True, waves_per_block=wpb, reorder_every=o["reorder_every"])
+    tune = g.autotune(5) if autotune else None
     info = g.info()
     sec, wall = timed_sweeps(g, steps, warmup)
     obs = g.observables(0)
     g.close()
+    info["autotune"] = tune
     return systems, info, sec, wall, obs
 
 
-def batched_vs_plain(steps, warmup):
+def shape_of(info):
+    return {"waves_per_block": info["waves_per_block"], "waves_per_cu": info["waves_per_cu"],
+            "xcd_remap": info["xcd_remap"], "autotuned": info.get("autotune") is not None}
+
+
+def batched_vs_plain(steps, warmup, autotune=True):
     """Batched launch of the 64 uneven systems vs each system alone, same sweeps."""
     import numpy as np
     from paper_2606_09356_amd import workloads as W
@@ -91,8 +100,10 @@ def batched_vs_plain(steps, warmup):
     B = sum(s.n_beads for s in systems)
     g = Soma(systems, seed=SEED, pos_repr=o["pos_repr"], count_width=o["count_width"], use_graph=True,
              reorder_every=o["reorder_every"])
+    tune = g.autotune(5) if autotune else None
     sec_b, _ = timed_sweeps(g, steps, warmup)
     info_b = g.info()
+    info_b["autotune"] = tune
     re2_b = [g.observables(k)["Re2"] for k in range(len(systems))]
     g.close()
     sec_p = 0.0
@@ -100,6 +111,8 @@ def batched_vs_plain(steps, warmup):
     for k, s in enumerate(systems):
         a = Soma([s], seed=SEED, pos_repr=o["pos_repr"], count_width=o["count_width"], use_graph=True,
                  sys_id_base=k, reorder_every=o["reorder_every"])
+        if autotune:
+            a.autotune(5)
         t, _ = timed_sweeps(a, steps, warmup)
         sec_p += t
         re2_p.append(a.observables(0)["Re2"])
@@ -113,13 +126,15 @@ def batched_vs_plain(steps, warmup):
         "plain_sequential_moves_per_s": B * steps / sec_p,
         "batched_over_plain": sec_p / sec_b,
         "batched_hbm_gbs": info_b["bytes_per_sweep"] * steps / sec_b / 1e9,
+        "batched_shape": shape_of(info_b), "plain_autotuned_each": bool(autotune),
         "re2_max_abs_diff_batched_vs_plain": float(np.abs(re2_b - re2_p).max()),
     }
 
 
-def measured_traffic(workload):
-    """HBM bytes per k_sweep launch from the committed rocprofv3 counter summary,
-    only while the kernel source is the one that was profiled (else None)."""
+def profiled(workload):
+    """The committed rocprofv3 counter summary of k_sweep (HBM bytes and
+    atomics per launch), only while the kernel source is the one that was
+    profiled (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_traffic.json")
     src = os.path.join(ROOT, "paper_2606_09356_amd", "csrc", "soma_kernels.hip")
@@ -128,7 +143,28 @@ def measured_traffic(workload):
     rec = json.load(open(path))
     if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec
+
+
+def atomic_calibration(n_words=1 << 21, n_ops=1 << 23, reps=5):
+    """Device-scope 32-bit atomic adds per second at random words of an 8 MiB
+    array (torch index_add_ on int32, which issues one atomic per element)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(SEED)
+    buf = torch.zeros(n_words, dtype=torch.int32, device="cuda")
+    idx = torch.randint(0, n_words, (n_ops,), device="cuda", generator=g)
+    one = torch.ones(n_ops, dtype=torch.int32, device="cuda")
+    buf.index_add_(0, idx, one)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        buf.index_add_(0, idx, one)
+    e1.record()
+    e1.synchronize()
+    assert int(buf.sum().item()) == (reps + 1) * n_ops
+    return n_ops * reps / (e0.elapsed_time(e1) / 1e3)
 
 
 def cpu_baseline(name, budget_s=15.0):
@@ -171,8 +207,11 @@ def main():
     load_library()
 
     print(f"[bench] workload {args.workload}: {args.warmup} warmup + {args.steps} timed sweeps", flush=True)
-    systems, info, sec, wall, obs = run_workload(args.workload, args.steps, args.warmup, args.waves_per_block)
+    autotune = not args.no_autotune
+    systems, info, sec, wall, obs = run_workload(args.workload, args.steps, args.warmup, args.waves_per_block,
+                                                 autotune)
     B = info["n_beads"]
+    prof = profiled(args.workload)
     moves_per_s = B * args.steps / sec
     ms_per_step = sec * 1e3 / args.steps
     achieved = info["bytes_per_sweep"] / (sec / args.steps) / 1e9
@@ -191,35 +230,51 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {len(systems)} system(s), {B} beads, {info['n_cells']} cells, "
                                "Gaussian-walk start, delta 0.05 Re, 128 beads/Re^3, cell Re/4",
-                   "beads": B, "sweeps_per_step": 1, "parallelism": "single GPU"},
+                   "beads": B, "sweeps_per_step": 1, "parallelism": "single GPU",
+                   "launch_shape": shape_of(info)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": prof["traffic_bytes_per_launch"] if prof else None,
                      "bytes_per_sweep": info["bytes_per_sweep"],
-                     "kernel": "k_sweep (move + density + field, one launch per sweep)",
+                     "kernel": "k_sweep + k_fold (move with fields from the counts; density delta "
+                               "folded into the counts), one pair of launches per sweep",
                      "avg_sweep_us_hip_events": sec / args.steps * 1e6},
         "observables": {k: obs[k] for k in ("Re2", "Re2_err", "Rg2", "Ebond_per_chain", "Enb_per_chain",
                                            "accept_ratio")},
         "wall_s": wall,
     }
+    print("[bench] atomic-rate calibration", flush=True)
+    peak_atomics = atomic_calibration()
+    atom = {"calibrated_peak_per_s": peak_atomics,
+            "calibration": "torch index_add_ of 2^23 ones at random words of an 8 MiB int32 array"}
+    if prof and prof.get("atomics_per_launch"):
+        kern_s = prof["k_sweep_avg_ns"] * 1e-9
+        atom.update({"atomics_per_sweep": prof["atomics_per_launch"],
+                     "achieved_per_s": prof["atomics_per_launch"] / kern_s,
+                     "frac": prof["atomics_per_launch"] / kern_s / peak_atomics,
+                     "source": "TCC_ATOMIC_sum and k_sweep duration from the committed rocprofv3 summary"})
+    out["roofline"]["atomics"] = atom
     if not args.no_extra:
         print("[bench] batched vs plain", flush=True)
-        out["batched_vs_plain"] = batched_vs_plain(min(args.steps, 200), min(args.warmup, 20))
+        out["batched_vs_plain"] = batched_vs_plain(min(args.steps, 200), min(args.warmup, 20), autotune)
         print("[bench] mixed precision workload", flush=True)
-        ms, minfo, msec, _, mobs = run_workload("mixed_large", min(args.steps, 200), min(args.warmup, 20))
+        ms, minfo, msec, _, mobs = run_workload("mixed_large", min(args.steps, 200), min(args.warmup, 20),
+                                                autotune=autotune)
         mst = min(args.steps, 200)
         out["mixed_large"] = {"moves_per_s": minfo["n_beads"] * mst / msec,
                               "hbm_gbs": minfo["bytes_per_sweep"] * mst / msec / 1e9,
                               "frac": minfo["bytes_per_sweep"] * mst / msec / 1e9 / HBM_PEAK_GBS,
-                              "beads": minfo["n_beads"], "Re2": mobs["Re2"]}
+                              "beads": minfo["n_beads"], "Re2": mobs["Re2"], "launch_shape": shape_of(minfo)}
         print("[bench] batched mixed-precision workload", flush=True)
-        bs, binfo, bsec, _, _ = run_workload("batched_mixed", min(args.steps, 100), min(args.warmup, 10))
+        bs, binfo, bsec, _, _ = run_workload("batched_mixed", min(args.steps, 100), min(args.warmup, 10),
+                                             autotune=autotune)
         bst = min(args.steps, 100)
         out["batched_mixed"] = {"workload": "256 systems of A/B blends, AB and ABA (N 8..128, 1e4..1e6 beads), "
                                             "int32 cell + FP32 offset, uint16 counts",
                                 "moves_per_s": binfo["n_beads"] * bst / bsec,
                                 "hbm_gbs": binfo["bytes_per_sweep"] * bst / bsec / 1e9,
                                 "frac": binfo["bytes_per_sweep"] * bst / bsec / 1e9 / HBM_PEAK_GBS,
-                                "beads": binfo["n_beads"], "systems": len(bs),
+                                "beads": binfo["n_beads"], "systems": len(bs), "launch_shape": shape_of(binfo),
                                 "over_plain_large": (binfo["n_beads"] * bst / bsec) / moves_per_s}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", flush=True)

@@ -96,7 +96,8 @@ typedef struct {
     int32_t pos_repr;          /* SOMA_POS_* */
     int32_t count_width;       /* SOMA_COUNT_* */
     int32_t use_graph;         /* nonzero: soma_mc_sweep replays a captured hipGraph per sweep count */
-    int32_t density_mode;      /* 0: global atomics, 1: LDS-privatised window, -1: pick by timing at create */
+    int32_t density_mode;      /* must be 0: accepted cell changes are added to a per-sweep
+                                  delta with device atomics and folded after the sweep */
     int32_t reorder_every;     /* >0: spatially sort chains every this many sweeps; 0: never */
     int32_t waves_per_block;   /* 1..16 waves per workgroup; 0: library default */
     int32_t waves_per_cu;      /* >0: sweep grid of this many waves per compute unit, each wave
@@ -124,7 +125,9 @@ typedef struct {
     uint64_t sweep;            /* sweeps done */
     int64_t bytes_per_sweep;   /* algorithmic HBM bytes of one sweep (positions, counts) */
     int32_t density_mode;      /* the variant in use */
-    int32_t waves_per_block;
+    int32_t waves_per_block;   /* launch shape in use (see soma_autotune) */
+    int32_t waves_per_cu;
+    int32_t xcd_remap;
 } soma_info;
 
 /* Bytes of device workspace that soma_create needs for these systems. */
@@ -194,6 +197,26 @@ int soma_release_fields(soma_ctx *ctx, int32_t sys);
 int soma_set_sweep(soma_ctx *ctx, uint64_t sweep);
 
 int soma_get_info(soma_ctx *ctx, soma_info *out);
+
+/* Launch-shape autotuning, the "adjusting launch configurations" step of
+ * the SOMA optimisation (Sec. 2.2).  For every candidate shape -- waves per
+ * workgroup in {1, 2, 4, 8, 16}; one tile per wave, or a resident grid of
+ * 8 or 32 waves per compute unit walking tile ranges; XCD-aware block order
+ * on or off -- times `trial_sweeps` sweeps (1..1000) after one warm-up
+ * sweep, and keeps the fastest shape for every later sweep.  The trial
+ * sweeps are undone: positions, counts, acceptance counters, the status
+ * word and the sweep counter are restored, so the trajectory is exactly
+ * the one of an untuned context (launch shapes never change results).
+ * Synchronises; out may be NULL.  SOMA_EINVAL for a bad trial count. */
+typedef struct {
+    int32_t waves_per_block;   /* chosen shape */
+    int32_t waves_per_cu;      /* 0: one tile per wave */
+    int32_t xcd_remap;
+    int32_t n_candidates;
+    double us_per_sweep;       /* trial time of the chosen shape */
+    double us_per_sweep_before;/* trial time of the shape in use at the call */
+} soma_tune;
+int soma_autotune(soma_ctx *ctx, int32_t trial_sweeps, soma_tune *out);
 
 /* Text of the last error of ctx (or of the last failed soma_create when
  * ctx is NULL).  Valid until the next call on the context. */

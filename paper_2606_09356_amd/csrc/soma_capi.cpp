@@ -54,6 +54,7 @@ struct soma_ctx {
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
     int repr = 0, cw = 0, waves_per_block = 4, xcd_remap = 1, density_mode = 0, max_blocks = 0;
+    int waves_per_cu = 0, n_cus = 0;
     uint64_t sweep = 0;
     uint64_t last_reorder = ~uint64_t(0);
     int latched = SOMA_OK;
@@ -112,7 +113,7 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
     if (opt->count_width != SOMA_COUNT_U16 && opt->count_width != SOMA_COUNT_U32) { msg = "bad count_width"; return SOMA_EINVAL; }
     if (opt->waves_per_block < 0 || opt->waves_per_block > 16) { msg = "waves_per_block must be 0..16"; return SOMA_EINVAL; }
     if (opt->waves_per_cu < 0 || opt->waves_per_cu > 64) { msg = "waves_per_cu must be 0..64"; return SOMA_EINVAL; }
-    if (opt->density_mode < -1 || opt->density_mode > 1) { msg = "density_mode must be -1, 0 or 1"; return SOMA_EINVAL; }
+    if (opt->density_mode != 0) { msg = "density_mode must be 0"; return SOMA_EINVAL; }
     if (opt->reorder_every < 0) { msg = "reorder_every must be >= 0"; return SOMA_EINVAL; }
     if (opt->sys_id_base < 0 || (int64_t)opt->sys_id_base + n_sys >= (int64_t(1) << 31)) { msg = "sys_id_base + n_sys must stay below 2^31"; return SOMA_EINVAL; }
     for (int32_t k = 0; k < n_sys; ++k) {
@@ -277,6 +278,25 @@ int sync_status(soma_ctx *c)
     if (st & soma::ST_NONFINITE) { c->latched = SOMA_ENONFINITE; return fail(c, SOMA_ENONFINITE, "non-finite field value"); }
     if (st & soma::ST_INTERNAL) { c->latched = SOMA_EDEVICE; return fail(c, SOMA_EDEVICE, "internal consistency check failed in the chain reorder"); }
     return SOMA_OK;
+}
+
+// Launch shape of the sweep kernel: waves per workgroup, resident grid
+// (waves per compute unit, 0 for one tile per wave) and block order.
+void set_shape(soma_ctx *c, int waves_per_block, int waves_per_cu, int xcd_remap)
+{
+    c->waves_per_block = waves_per_block;
+    c->waves_per_cu = waves_per_cu;
+    c->xcd_remap = xcd_remap;
+    c->max_blocks = waves_per_cu > 0 ? std::max(1, waves_per_cu * c->n_cus / waves_per_block) : 0;
+}
+
+// Captured graphs hold the launch shape in their kernel nodes.
+void drop_graphs(soma_ctx *c)
+{
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t g : c->graph_defs) (void)hipGraphDestroy(g);
+    c->graphs.clear();
+    c->graph_defs.clear();
 }
 
 soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
@@ -537,15 +557,6 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
     c->waves_per_block = opt->waves_per_block > 0 ? opt->waves_per_block : 4;
     c->density_mode = 0;
     c->stream = reinterpret_cast<hipStream_t>(opt->hip_stream);
-    if (opt->waves_per_cu > 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
-            delete c;
-            return fail(nullptr, SOMA_EDEVICE, "cannot query the compute-unit count");
-        }
-        c->max_blocks = std::max(1, opt->waves_per_cu * cus / c->waves_per_block);
-    }
     c->L = plan(sys, n_sys, opt, &c->sys);
     if (workspace_bytes < c->L.total) {
         char b[128];
@@ -553,6 +564,16 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
         delete c;
         return fail(nullptr, SOMA_ENOMEM, b);
     }
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+            delete c;
+            return fail(nullptr, SOMA_EDEVICE, "cannot query the compute-unit count");
+        }
+        c->n_cus = cus;
+    }
+    set_shape(c, c->waves_per_block, opt->waves_per_cu, 1);
     c->ws = static_cast<char *>(workspace);
     for (size_t k = 0; k < c->sys.size(); ++k) {
         const HostSys &h = c->sys[k];
@@ -609,8 +630,7 @@ int soma_destroy(soma_ctx *c)
 {
     if (!c) return SOMA_EINVAL;
     if (c->ws) (void)hipStreamSynchronize(c->stream);
-    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-    for (hipGraph_t g : c->graph_defs) (void)hipGraphDestroy(g);
+    drop_graphs(c);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;
     return SOMA_OK;
@@ -898,7 +918,85 @@ int soma_get_info(soma_ctx *c, soma_info *out)
     out->bytes_per_sweep = 2 * pos * beads + 4 * cnt * cells;
     out->density_mode = c->density_mode;
     out->waves_per_block = c->waves_per_block;
+    out->waves_per_cu = c->waves_per_cu;
+    out->xcd_remap = c->xcd_remap;
     return SOMA_OK;
+}
+
+int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if (trial_sweeps < 1 || trial_sweeps > 1000) return fail(c, SOMA_EINVAL, "trial_sweeps must be in [1, 1000]");
+    const int n_sys = (int)c->sys.size();
+    const size_t pos_bytes = sizeof(float) * (size_t)c->L.total_slots;
+    const size_t acc_words = 2 * (size_t)soma::kAcceptSlots * soma::kAcceptStride * n_sys;
+    std::vector<uint32_t> acc(acc_words), status(16);
+    uint64_t ctr = 0;
+    // save what trial sweeps change: positions (to the reorder scratch),
+    // acceptance counters, status and the device sweep counter
+    for (int d = 0; d < 3; ++d) {
+        HIPCHK(c, hipMemcpyAsync(c->Q(d), c->P(d), pos_bytes, hipMemcpyDeviceToDevice, c->stream));
+        if (c->repr == soma::REPR_CELL)
+            HIPCHK(c, hipMemcpyAsync(c->D(d), c->C(d), pos_bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(acc.data(), c->accept(), acc_words * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(status.data(), c->status(), 16 * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&ctr, c->sweep_ctr(), sizeof ctr, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    auto time_shape = [&](int wpb, int wpcu, int xcd, double &us) -> int {
+        set_shape(c, wpb, wpcu, xcd);
+        if ((rc = record_sweeps(c, 1, c->stream)) != SOMA_OK) return rc;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        if ((rc = record_sweeps(c, trial_sweeps, c->stream)) != SOMA_OK) return rc;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        us = 1e3 * (double)ms / trial_sweeps;
+        return SOMA_OK;
+    };
+    soma_tune best{c->waves_per_block, c->waves_per_cu, c->xcd_remap, 0, 0.0, 0.0};
+    const int before[3] = {c->waves_per_block, c->waves_per_cu, c->xcd_remap};
+    rc = time_shape(before[0], before[1], before[2], best.us_per_sweep_before);
+    best.us_per_sweep = best.us_per_sweep_before;
+    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32}, kXcd[] = {1, 0};
+    for (int wpb : kWpb)
+        for (int wpcu : kWpcu)
+            for (int xcd : kXcd) {
+                if (rc != SOMA_OK) break;
+                double us = 0.0;
+                rc = time_shape(wpb, wpcu, xcd, us);
+                ++best.n_candidates;
+                if (rc == SOMA_OK && us < best.us_per_sweep) {
+                    best.us_per_sweep = us;
+                    best.waves_per_block = wpb;
+                    best.waves_per_cu = wpcu;
+                    best.xcd_remap = xcd;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SOMA_OK) return rc;
+    set_shape(c, best.waves_per_block, best.waves_per_cu, best.xcd_remap);
+    drop_graphs(c);
+
+    // undo the trial sweeps
+    for (int d = 0; d < 3; ++d) {
+        HIPCHK(c, hipMemcpyAsync(c->P(d), c->Q(d), pos_bytes, hipMemcpyDeviceToDevice, c->stream));
+        if (c->repr == soma::REPR_CELL)
+            HIPCHK(c, hipMemcpyAsync(c->C(d), c->D(d), pos_bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->accept(), acc.data(), acc_words * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->status(), status.data(), 16 * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->sweep_ctr(), &ctr, sizeof ctr, hipMemcpyHostToDevice, c->stream));
+    if ((rc = rebuild_density(c, -1)) != SOMA_OK) return rc;
+    if (out) *out = best;
+    return sync_status(c);
 }
 
 const char *soma_last_error(const soma_ctx *c)

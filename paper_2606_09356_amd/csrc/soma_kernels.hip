@@ -602,13 +602,29 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     }
 }
 
-// Fold the sweep's density delta into the counts and clear it.
+// Fold the sweep's density delta into the counts and clear it: 16-byte
+// accesses (both arrays are 256-byte aligned), then the words past the last
+// full quadruple.
 template <int CW>
 __global__ __launch_bounds__(256) void k_fold(uint32_t *counts, uint32_t *delta, int64_t n, uint32_t *status)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n4 = n >> 2;
+    uint4 *c4 = reinterpret_cast<uint4 *>(counts);
+    uint4 *d4 = reinterpret_cast<uint4 *>(delta);
     bool ovf = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    for (int64_t i = tid; i < n4; i += stride) {
+        const uint4 b = c4[i], d = d4[i];
+        uint4 w;
+        ovf |= fold_word<CW>(b.x, d.x, w.x);
+        ovf |= fold_word<CW>(b.y, d.y, w.y);
+        ovf |= fold_word<CW>(b.z, d.z, w.z);
+        ovf |= fold_word<CW>(b.w, d.w, w.w);
+        c4[i] = w;
+        d4[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    for (int64_t i = 4 * n4 + tid; i < n; i += stride) {
         uint32_t w;
         ovf |= fold_word<CW>(counts[i], delta[i], w);
         counts[i] = w;
@@ -1104,8 +1120,8 @@ hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off
 hipError_t launch_fold(int cw, uint32_t *counts, uint32_t *delta, int64_t n, uint32_t *status, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
+    int64_t blocks = ((n + 3) / 4 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
     if (cw == COUNT_U16) hipLaunchKernelGGL((k_fold<COUNT_U16>), dim3((unsigned)blocks), dim3(256), 0, st, counts, delta, n, status);
     else hipLaunchKernelGGL((k_fold<COUNT_U32>), dim3((unsigned)blocks), dim3(256), 0, st, counts, delta, n, status);
     return hipGetLastError();

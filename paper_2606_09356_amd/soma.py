@@ -56,13 +56,20 @@ class soma_obs(C.Structure):
 class soma_info(C.Structure):
     _fields_ = [("n_systems", C.c_int32), ("n_tiles", C.c_int32), ("n_beads", C.c_int64),
                 ("n_cells", C.c_int64), ("sweep", C.c_uint64), ("bytes_per_sweep", C.c_int64),
-                ("density_mode", C.c_int32), ("waves_per_block", C.c_int32)]
+                ("density_mode", C.c_int32), ("waves_per_block", C.c_int32),
+                ("waves_per_cu", C.c_int32), ("xcd_remap", C.c_int32)]
+
+
+class soma_tune(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int32), ("waves_per_cu", C.c_int32), ("xcd_remap", C.c_int32),
+                ("n_candidates", C.c_int32), ("us_per_sweep", C.c_double),
+                ("us_per_sweep_before", C.c_double)]
 
 
 EXPORTS = ("soma_workspace_size", "soma_create", "soma_destroy", "soma_mc_sweep", "soma_sync",
            "soma_density", "soma_fields", "soma_observables", "soma_get_positions",
            "soma_set_positions", "soma_get_state", "soma_set_state", "soma_set_fields",
-           "soma_release_fields", "soma_set_sweep", "soma_get_info", "soma_last_error")
+           "soma_release_fields", "soma_set_sweep", "soma_get_info", "soma_autotune", "soma_last_error")
 
 _lib = None
 
@@ -98,6 +105,7 @@ def load_library(path: str = LIB_PATH):
         "soma_release_fields": ([P, I32], C.c_int),
         "soma_set_sweep": ([P, C.c_uint64], C.c_int),
         "soma_get_info": ([P, P], C.c_int),
+        "soma_autotune": ([P, I32, P], C.c_int),
         "soma_last_error": ([P], C.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -203,6 +211,12 @@ class Soma:
         i = soma_info()
         self._c(self.lib.soma_get_info(self.ctx, C.byref(i)))
         return {f: getattr(i, f) for f, _ in soma_info._fields_}
+
+    def autotune(self, trial_sweeps: int = 5) -> dict:
+        """Time every launch shape and keep the fastest; trial sweeps are undone."""
+        t = soma_tune()
+        self._c(self.lib.soma_autotune(self.ctx, trial_sweeps, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in soma_tune._fields_}
 
     def density(self, sys: int = 0) -> np.ndarray:
         M = self.systems[sys].n_cells

@@ -90,3 +90,7 @@ def test_create_rejects_short_or_misaligned_workspace(lib):
     aligned = (addr + 255) & ~255
     assert lib.soma_create(arr, 1, C.byref(_opts()), aligned, 1024, C.byref(ctx)) == S.SOMA_ENOMEM
     assert not ctx.value
+
+
+def test_autotune_rejects_null_context(lib):
+    assert lib.soma_autotune(None, 5, None) == S.SOMA_EINVAL

@@ -203,6 +203,39 @@ def test_graph_tiling_and_xcd_invariance():
         g.close()
 
 
+def _same_state(x, y):
+    if isinstance(x, tuple):
+        return all(np.array_equal(a, b) for a, b in zip(x, y))
+    return np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("r", ["f32", "cell"])
+def test_autotune_keeps_the_trajectory(r):
+    """Autotuning times every launch shape on trial sweeps and undoes them:
+    the tuned context then continues exactly like an untuned one."""
+    systems = W.batched_mixed(n_systems=4, seed=48, bead_range=(2000, 12000))
+    a = Soma(systems, seed=SEED, pos_repr=r, count_width=16, reorder_every=3)
+    b = Soma(systems, seed=SEED, pos_repr=r, count_width=16, reorder_every=3)
+    a.sweep(2)
+    b.sweep(2)
+    t = a.autotune(trial_sweeps=2)
+    print(f"[autotune {r}] {t}", flush=True)
+    assert t["n_candidates"] == 30 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
+    i = a.info()
+    assert (i["waves_per_block"], i["waves_per_cu"], i["xcd_remap"]) == \
+        (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"])
+    assert i["sweep"] == 2
+    a.sweep(5)
+    b.sweep(5)
+    for k in range(len(systems)):
+        assert _same_state(a.state(k), b.state(k)), k
+        assert (a.density(k) == b.density(k)).all(), k
+        oa, ob = a.observables(k), b.observables(k)
+        assert (oa["n_moves"], oa["n_accepted"], oa["sweep"]) == (ob["n_moves"], ob["n_accepted"], ob["sweep"]), k
+    a.close()
+    b.close()
+
+
 def test_batched_equals_each_system_alone():
     systems = W.batched_uneven(n_systems=5, seed=47, chain_range=(64, 500))
     g = Soma(systems, seed=SEED, pos_repr="f32", count_width=16)
