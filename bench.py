@@ -44,9 +44,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run one 1 GiB device copy (reference for HBM byte counters) and exit")
-    p.add_argument("--waves-per-block", type=int, default=0)
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default launch shape instead of timing every shape first")
+    p.add_argument("--shape", default=None,
+                   help="fixed launch shape WPB,WPCU,ORDER,DM for the main workload (no autotuning): "
+                        "waves per block, waves per CU (0: one tile per wave), launch_order, density_mode")
     return p.parse_args()
 
 
@@ -69,14 +71,16 @@ def timed_sweeps(g, steps, warmup):
     return start.elapsed_time(end) / 1e3, wall
 
 
-def run_workload(name, steps, warmup, wpb=0, autotune=True):
+def run_workload(name, steps, warmup, shape=None, autotune=True):
     from paper_2606_09356_amd import workloads as W
     from paper_2606_09356_amd.soma import Soma
     systems = W.workload(name)
     o = W.WORKLOAD_OPTIONS[name]
+    wpb, wpcu, order, dm = shape if shape else (0, 0, 0, 0)
     g = Soma(systems, seed=SEED, pos_repr=o["pos_repr"], count_width=o["count_width"],
-             use_graph=True, waves_per_block=wpb, reorder_every=o["reorder_every"])
-    tune = g.autotune(5) if autotune else None
+             use_graph=True, waves_per_block=wpb, waves_per_cu=wpcu, launch_order=order, density_mode=dm,
+             reorder_every=o["reorder_every"])
+    tune = g.autotune(5) if autotune and not shape else None
     info = g.info()
     sec, wall = timed_sweeps(g, steps, warmup)
     obs = g.observables(0)
@@ -87,7 +91,8 @@ def run_workload(name, steps, warmup, wpb=0, autotune=True):
 
 def shape_of(info):
     return {"waves_per_block": info["waves_per_block"], "waves_per_cu": info["waves_per_cu"],
-            "xcd_remap": info["xcd_remap"], "autotuned": info.get("autotune") is not None}
+            "xcd_remap": info["xcd_remap"], "density_mode": info["density_mode"],
+            "autotuned": info.get("autotune") is not None}
 
 
 def batched_vs_plain(steps, warmup, autotune=True):
@@ -208,8 +213,8 @@ def main():
 
     print(f"[bench] workload {args.workload}: {args.warmup} warmup + {args.steps} timed sweeps", flush=True)
     autotune = not args.no_autotune
-    systems, info, sec, wall, obs = run_workload(args.workload, args.steps, args.warmup, args.waves_per_block,
-                                                 autotune)
+    shape = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
+    systems, info, sec, wall, obs = run_workload(args.workload, args.steps, args.warmup, shape, autotune)
     B = info["n_beads"]
     prof = profiled(args.workload)
     moves_per_s = B * args.steps / sec

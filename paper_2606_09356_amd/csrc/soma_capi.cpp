@@ -55,6 +55,10 @@ struct soma_ctx {
     hipStream_t capture_stream = nullptr;
     int repr = 0, cw = 0, waves_per_block = 4, xcd_remap = 1, density_mode = 0, max_blocks = 0;
     int waves_per_cu = 0, n_cus = 0;
+    // density_mode 1 keeps the counts in rotation (base[(s+1)&1] + delta[(s+2)%3]
+    // before sweep s); `rot` says the buffers are in that layout.  Otherwise
+    // (canonical) the counts are base[0] and every delta is zero.
+    bool rot = false;
     uint64_t sweep = 0;
     uint64_t last_reorder = ~uint64_t(0);
     int latched = SOMA_OK;
@@ -70,9 +74,11 @@ struct soma_ctx {
     int *D(int d) const { return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + L.D[d]) : nullptr; }
     uint32_t *chain_id() const { return reinterpret_cast<uint32_t *>(ws + L.chain_id); }
     uint32_t *u32(size_t off) const { return reinterpret_cast<uint32_t *>(ws + off); }
-    // Current counts; the density delta of a sweep is folded in right after it.
-    uint32_t *counts() const { return reinterpret_cast<uint32_t *>(ws + L.base); }
-    uint32_t *delta() const { return reinterpret_cast<uint32_t *>(ws + L.delta); }
+    // Count buffers base[0..1] and delta buffers delta[0..2], count_words each.
+    uint32_t *base(int k) const { return reinterpret_cast<uint32_t *>(ws + L.base) + k * L.count_words; }
+    uint32_t *delta(int k) const { return reinterpret_cast<uint32_t *>(ws + L.delta) + k * L.count_words; }
+    // Counts in the canonical layout.
+    uint32_t *counts() const { return base(0); }
     float2 *omega() const { return reinterpret_cast<float2 *>(ws + L.omega); }
     unsigned long long *accept() const { return reinterpret_cast<unsigned long long *>(ws + L.accept); }
     uint32_t *status() const { return reinterpret_cast<uint32_t *>(ws + L.status); }
@@ -113,8 +119,9 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
     if (opt->count_width != SOMA_COUNT_U16 && opt->count_width != SOMA_COUNT_U32) { msg = "bad count_width"; return SOMA_EINVAL; }
     if (opt->waves_per_block < 0 || opt->waves_per_block > 16) { msg = "waves_per_block must be 0..16"; return SOMA_EINVAL; }
     if (opt->waves_per_cu < 0 || opt->waves_per_cu > 64) { msg = "waves_per_cu must be 0..64"; return SOMA_EINVAL; }
-    if (opt->density_mode != 0) { msg = "density_mode must be 0"; return SOMA_EINVAL; }
+    if (opt->density_mode != 0 && opt->density_mode != 1) { msg = "density_mode must be 0 or 1"; return SOMA_EINVAL; }
     if (opt->reorder_every < 0) { msg = "reorder_every must be >= 0"; return SOMA_EINVAL; }
+    if (opt->launch_order != 0 && opt->launch_order != 1) { msg = "launch_order must be 0 or 1"; return SOMA_EINVAL; }
     if (opt->sys_id_base < 0 || (int64_t)opt->sys_id_base + n_sys >= (int64_t(1) << 31)) { msg = "sys_id_base + n_sys must stay below 2^31"; return SOMA_EINVAL; }
     for (int32_t k = 0; k < n_sys; ++k) {
         const soma_system_desc &d = sys[k];
@@ -242,8 +249,8 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     L.hist = take(sizeof(uint32_t) * cells);
     L.bsum = take(sizeof(uint32_t) * soma::reorder_bsum_words(cells));
     L.perm = take(sizeof(uint32_t) * chains);
-    L.base = take(sizeof(uint32_t) * L.count_words);
-    L.delta = take(sizeof(uint32_t) * L.count_words);
+    L.base = take(sizeof(uint32_t) * 2 * L.count_words);
+    L.delta = take(sizeof(uint32_t) * 3 * L.count_words);
     L.omega = take(sizeof(float) * 2 * cells);
     L.accept = take(sizeof(uint64_t) * soma::kAcceptSlots * soma::kAcceptStride * n_sys);
     L.status = take(64);
@@ -313,9 +320,10 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
         (&a.P0)[d] = c->P(d);
         (&a.C0)[d] = c->C(d);
     }
-    a.counts = c->counts();
-    a.delta = c->delta();
+    a.base = c->base(0);
+    a.delta = c->delta(0);
     a.count_words = c->L.count_words;
+    a.fold_in = c->density_mode;
     a.omega = c->omega();
     a.sweep_ctr = c->sweep_ctr();
     a.rel = rel;
@@ -325,21 +333,53 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
     return a;
 }
 
-// Rebuild the density of one system (or all when sys < 0) as the current
-// base counts with a zero delta.
+// Bring the count buffers to the canonical layout (counts in base[0], every
+// delta zero) from the rotation of density mode 1 before sweep c->sweep.
+int canonicalize(soma_ctx *c)
+{
+    if (!c->rot) return SOMA_OK;
+    const uint64_t s = c->sweep;
+    HIPCHK(c, soma::launch_fold(c->cw, c->base((int)((s + 1) & 1)), c->delta((int)((s + 2) % 3)), c->base(0),
+                                c->L.count_words, c->status(), c->stream));
+    HIPCHK(c, soma::launch_fill_u32(c->delta(0), 3 * c->L.count_words, 0u, c->stream));
+    c->rot = false;
+    return SOMA_OK;
+}
+
+// From the canonical layout to the rotation before sweep c->sweep: its
+// counts B[s-1] + D[s-1] are base[(s+1)&1] + delta[(s+2)%3], its delta
+// delta[s%3] starts at zero.
+int enter_rotation(soma_ctx *c)
+{
+    if (c->rot) return SOMA_OK;
+    const int k = (int)((c->sweep + 1) & 1);
+    if (k != 0)
+        HIPCHK(c, hipMemcpyAsync(c->base(k), c->base(0), sizeof(uint32_t) * c->L.count_words,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    c->rot = true;
+    return SOMA_OK;
+}
+
+// The layout the context's density mode sweeps in.
+int sweep_layout(soma_ctx *c)
+{
+    return c->density_mode == 1 ? enter_rotation(c) : canonicalize(c);
+}
+
+// Rebuild the density of one system (or all when sys < 0) in the canonical
+// layout.
 int rebuild_density(soma_ctx *c, int32_t sys)
 {
+    int rc = canonicalize(c);
+    if (rc != SOMA_OK) return rc;
     uint32_t *cur = c->counts();
-    uint32_t *dcur = c->delta();
     const int64_t wpc = c->words_per_cell();
     int tb = 0, te = c->L.n_tiles;
     if (sys < 0) {
         HIPCHK(c, soma::launch_fill_u32(cur, c->L.count_words, 0u, c->stream));
-        HIPCHK(c, soma::launch_fill_u32(dcur, c->L.count_words, 0u, c->stream));
     } else {
         const HostSys &h = c->sys[sys];
         HIPCHK(c, soma::launch_fill_u32(cur + h.dev.cell_off * wpc, h.dev.n_cells * wpc, 0u, c->stream));
-        HIPCHK(c, soma::launch_fill_u32(dcur + h.dev.cell_off * wpc, h.dev.n_cells * wpc, 0u, c->stream));
         tb = h.tile_begin;
         te = h.tile_end;
     }
@@ -412,7 +452,8 @@ int record_sweeps(soma_ctx *c, int32_t n, hipStream_t st)
     for (int32_t r = 0; r < n; ++r) {
         soma::SweepArgs a = sweep_args(c, (uint32_t)r);
         HIPCHK(c, soma::launch_sweep(c->repr, c->cw, a, st));
-        HIPCHK(c, soma::launch_fold(c->cw, c->counts(), c->delta(), c->L.count_words, c->status(), st));
+        if (c->density_mode == 0)
+            HIPCHK(c, soma::launch_fold(c->cw, c->counts(), c->delta(0), c->counts(), c->L.count_words, c->status(), st));
     }
     HIPCHK(c, soma::launch_advance(c->sweep_ctr(), (uint32_t)n, st));
     return SOMA_OK;
@@ -555,7 +596,7 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
     c->repr = opt->pos_repr == SOMA_POS_CELL_F32 ? soma::REPR_CELL : soma::REPR_F32;
     c->cw = opt->count_width == SOMA_COUNT_U32 ? soma::COUNT_U32 : soma::COUNT_U16;
     c->waves_per_block = opt->waves_per_block > 0 ? opt->waves_per_block : 4;
-    c->density_mode = 0;
+    c->density_mode = opt->density_mode;
     c->stream = reinterpret_cast<hipStream_t>(opt->hip_stream);
     c->L = plan(sys, n_sys, opt, &c->sys);
     if (workspace_bytes < c->L.total) {
@@ -573,7 +614,7 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
         }
         c->n_cus = cus;
     }
-    set_shape(c, c->waves_per_block, opt->waves_per_cu, 1);
+    set_shape(c, c->waves_per_block, opt->waves_per_cu, opt->launch_order == 0 ? 1 : 0);
     c->ws = static_cast<char *>(workspace);
     for (size_t k = 0; k < c->sys.size(); ++k) {
         const HostSys &h = c->sys[k];
@@ -590,8 +631,8 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
         return bail(hip_fail(c, e, "upload tiles"));
     // clear counts, fields, accept counters, status and sweep counter
     if ((rc = [&] {
-             HIPCHK(c, soma::launch_fill_u32(c->counts(), c->L.count_words, 0u, c->stream));
-             HIPCHK(c, soma::launch_fill_u32(c->delta(), c->L.count_words, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(c->base(0), 2 * c->L.count_words, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(c->delta(0), 3 * c->L.count_words, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->omega()), 2 * c->L.total_cells, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->accept()),
                                              2 * (int64_t)soma::kAcceptSlots * soma::kAcceptStride * n_sys, 0u, c->stream));
@@ -641,6 +682,7 @@ int soma_mc_sweep(soma_ctx *c, int32_t n)
     int rc = check_ctx(c);
     if (rc != SOMA_OK) return rc;
     if (n < 0) return fail(c, SOMA_EINVAL, "n_sweeps must be >= 0");
+    if (n > 0 && (rc = sweep_layout(c)) != SOMA_OK) return rc;
     const uint64_t R = (uint64_t)c->opt.reorder_every;
     int32_t left = n;
     while (left > 0) {
@@ -677,6 +719,7 @@ int soma_density(soma_ctx *c, int32_t sys, uint32_t *dst, int32_t dst_on_device)
     if (rc != SOMA_OK) return rc;
     if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
     if (!dst) return fail(c, SOMA_EINVAL, "dst is null");
+    if ((rc = canonicalize(c)) != SOMA_OK) return rc;
     const HostSys &h = c->sys[sys];
     uint32_t *target = dst_on_device ? dst : static_cast<uint32_t *>(c->staging());
     HIPCHK(c, soma::launch_unpack_counts(c->cw, c->counts(), h.dev.cell_off, h.dev.n_cells, target, c->stream));
@@ -691,6 +734,7 @@ int soma_fields(soma_ctx *c, int32_t sys, float *dst, int32_t dst_on_device)
     if (rc != SOMA_OK) return rc;
     if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
     if (!dst) return fail(c, SOMA_EINVAL, "dst is null");
+    if ((rc = canonicalize(c)) != SOMA_OK) return rc;
     const HostSys &h = c->sys[sys];
     soma::FieldArgs f{};
     f.systems = c->d_sys();
@@ -711,6 +755,7 @@ int soma_observables(soma_ctx *c, int32_t sys, soma_obs *out)
     if (rc != SOMA_OK) return rc;
     if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
     if (!out) return fail(c, SOMA_EINVAL, "out is null");
+    if ((rc = canonicalize(c)) != SOMA_OK) return rc;
     const HostSys &h = c->sys[sys];
     soma::ObsArgs a{};
     a.repr = c->repr;
@@ -890,10 +935,11 @@ int soma_set_sweep(soma_ctx *c, uint64_t sweep)
 {
     int rc = check_ctx(c);
     if (rc != SOMA_OK) return rc;
+    // leave the rotation while the counter still names its buffers
+    if ((rc = canonicalize(c)) != SOMA_OK) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->sweep_ctr(), &sweep, sizeof sweep, hipMemcpyHostToDevice));
     c->sweep = sweep;
-    HIPCHK(c, soma::launch_fill_u32(c->delta(), c->L.count_words, 0u, c->stream));
     if ((rc = rebuild_density(c, -1)) != SOMA_OK) return rc;
     return sync_status(c);
 }
@@ -933,6 +979,8 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
     const size_t acc_words = 2 * (size_t)soma::kAcceptSlots * soma::kAcceptStride * n_sys;
     std::vector<uint32_t> acc(acc_words), status(16);
     uint64_t ctr = 0;
+    const uint64_t host_sweep = c->sweep;
+    if ((rc = canonicalize(c)) != SOMA_OK) return rc;
     // save what trial sweeps change: positions (to the reorder scratch),
     // acceptance counters, status and the device sweep counter
     for (int d = 0; d < 3; ++d) {
@@ -945,14 +993,46 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
     HIPCHK(c, hipMemcpyAsync(&ctr, c->sweep_ctr(), sizeof ctr, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
 
+    // Every candidate starts from the saved state and runs the same sweeps
+    // (same counters, so the same moves): one warm-up batch, then the timed
+    // batch, launched the way soma_mc_sweep launches them (one captured
+    // graph, or eager launches without graphs).  The host sweep count
+    // follows the device counter meanwhile, so that the rotation of density
+    // mode 1 names the right buffers.
+    auto restore = [&]() -> int {
+        if ((rc = canonicalize(c)) != SOMA_OK) return rc;
+        c->sweep = host_sweep;
+        for (int d = 0; d < 3; ++d) {
+            HIPCHK(c, hipMemcpyAsync(c->P(d), c->Q(d), pos_bytes, hipMemcpyDeviceToDevice, c->stream));
+            if (c->repr == soma::REPR_CELL)
+                HIPCHK(c, hipMemcpyAsync(c->C(d), c->D(d), pos_bytes, hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIPCHK(c, hipMemcpyAsync(c->sweep_ctr(), &ctr, sizeof ctr, hipMemcpyHostToDevice, c->stream));
+        return rebuild_density(c, -1);
+    };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    auto time_shape = [&](int wpb, int wpcu, int xcd, double &us) -> int {
+    auto batch = [&]() -> int {
+        if (c->opt.use_graph) {
+            hipGraphExec_t ex;
+            if ((rc = graph_for(c, trial_sweeps, &ex)) != SOMA_OK) return rc;
+            HIPCHK(c, hipGraphLaunch(ex, c->stream));
+        } else if ((rc = record_sweeps(c, trial_sweeps, c->stream)) != SOMA_OK) {
+            return rc;
+        }
+        c->sweep += (uint64_t)trial_sweeps;
+        return SOMA_OK;
+    };
+    auto time_shape = [&](int wpb, int wpcu, int xcd, int dm, double &us) -> int {
+        if ((rc = restore()) != SOMA_OK) return rc;
         set_shape(c, wpb, wpcu, xcd);
-        if ((rc = record_sweeps(c, 1, c->stream)) != SOMA_OK) return rc;
+        c->density_mode = dm;
+        drop_graphs(c);
+        if ((rc = sweep_layout(c)) != SOMA_OK) return rc;
+        if ((rc = batch()) != SOMA_OK) return rc;
         HIPCHK(c, hipEventRecord(e0, c->stream));
-        if ((rc = record_sweeps(c, trial_sweeps, c->stream)) != SOMA_OK) return rc;
+        if ((rc = batch()) != SOMA_OK) return rc;
         HIPCHK(c, hipEventRecord(e1, c->stream));
         HIPCHK(c, hipEventSynchronize(e1));
         float ms = 0.0f;
@@ -960,41 +1040,38 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
         us = 1e3 * (double)ms / trial_sweeps;
         return SOMA_OK;
     };
-    soma_tune best{c->waves_per_block, c->waves_per_cu, c->xcd_remap, 0, 0.0, 0.0};
-    const int before[3] = {c->waves_per_block, c->waves_per_cu, c->xcd_remap};
-    rc = time_shape(before[0], before[1], before[2], best.us_per_sweep_before);
+    soma_tune best{c->waves_per_block, c->waves_per_cu, c->xcd_remap, c->density_mode, 0, 0.0, 0.0};
+    rc = time_shape(best.waves_per_block, best.waves_per_cu, best.xcd_remap, best.density_mode,
+                    best.us_per_sweep_before);
     best.us_per_sweep = best.us_per_sweep_before;
-    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32}, kXcd[] = {1, 0};
-    for (int wpb : kWpb)
-        for (int wpcu : kWpcu)
-            for (int xcd : kXcd) {
-                if (rc != SOMA_OK) break;
-                double us = 0.0;
-                rc = time_shape(wpb, wpcu, xcd, us);
-                ++best.n_candidates;
-                if (rc == SOMA_OK && us < best.us_per_sweep) {
-                    best.us_per_sweep = us;
-                    best.waves_per_block = wpb;
-                    best.waves_per_cu = wpcu;
-                    best.xcd_remap = xcd;
+    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32}, kXcd[] = {1, 0}, kDm[] = {0, 1};
+    for (int dm : kDm)
+        for (int wpb : kWpb)
+            for (int wpcu : kWpcu)
+                for (int xcd : kXcd) {
+                    if (rc != SOMA_OK) break;
+                    double us = 0.0;
+                    rc = time_shape(wpb, wpcu, xcd, dm, us);
+                    ++best.n_candidates;
+                    if (rc == SOMA_OK && us < best.us_per_sweep) {
+                        best.us_per_sweep = us;
+                        best.waves_per_block = wpb;
+                        best.waves_per_cu = wpcu;
+                        best.xcd_remap = xcd;
+                        best.density_mode = dm;
+                    }
                 }
-            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SOMA_OK) return rc;
     set_shape(c, best.waves_per_block, best.waves_per_cu, best.xcd_remap);
+    c->density_mode = best.density_mode;
     drop_graphs(c);
 
     // undo the trial sweeps
-    for (int d = 0; d < 3; ++d) {
-        HIPCHK(c, hipMemcpyAsync(c->P(d), c->Q(d), pos_bytes, hipMemcpyDeviceToDevice, c->stream));
-        if (c->repr == soma::REPR_CELL)
-            HIPCHK(c, hipMemcpyAsync(c->C(d), c->D(d), pos_bytes, hipMemcpyDeviceToDevice, c->stream));
-    }
+    if ((rc = restore()) != SOMA_OK) return rc;
     HIPCHK(c, hipMemcpyAsync(c->accept(), acc.data(), acc_words * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->status(), status.data(), 16 * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->sweep_ctr(), &ctr, sizeof ctr, hipMemcpyHostToDevice, c->stream));
-    if ((rc = rebuild_density(c, -1)) != SOMA_OK) return rc;
     if (out) *out = best;
     return sync_status(c);
 }

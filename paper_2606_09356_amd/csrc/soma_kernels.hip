@@ -20,8 +20,12 @@
 //   * The density is updated, not rebuilt: a sweep reads the counts C
 //     (frozen, for the fields) and adds -1/+1 atomically to a delta D only
 //     for accepted moves that change cell (about 0.2 of the beads), not one
-//     atomic per bead.  A short streaming kernel then folds C += D, D = 0;
-//     the fields of the next sweep follow from the folded counts.
+//     atomic per bead.  Two placements of the fold C += D, D = 0:
+//     a short streaming kernel after each sweep, or the next sweep's own
+//     threads: sweep s then reads its counts as B[s-1] + D[s-1], writes
+//     B[s] = B[s-1] + D[s-1], adds its changes to D[s] and clears D[s+1]
+//     (two base and three delta buffers in rotation), so the fold traffic
+//     overlaps the move work.
 //   * Philox4x32-10 is counter based: one 128-bit block per (bead, logical
 //     chain, sweep, system); no RNG state lives in memory.
 #include <hip/hip_runtime.h>
@@ -304,28 +308,44 @@ __device__ __forceinline__ uint2 load_counts(const uint32_t *cnt, int64_t cell)
     }
 }
 
-// Raw count words of one cell, loaded without being unpacked so that several
-// gathers can be in flight before the first use.
+// Raw count words of one cell (and, when the fold runs inside the sweep, the
+// words of the previous delta), loaded without being combined so that
+// several gathers can be in flight before the first use.
 struct RawCount {
-    uint32_t w0, w1;
+    uint32_t w0, w1, d0, d1;
 };
 
-template <int CW>
-__device__ __forceinline__ RawCount load_raw(const uint32_t *cnt, int64_t cell)
+template <int CW, bool FI>
+__device__ __forceinline__ RawCount load_raw(const uint32_t *cnt, const uint32_t *dprev, int64_t cell)
 {
+    RawCount r{0u, 0u, 0u, 0u};
     if constexpr (CW == COUNT_U16) {
-        return RawCount{cnt[cell], 0u};
+        r.w0 = cnt[cell];
+        if constexpr (FI) r.d0 = dprev[cell];
     } else {
         const uint2 w = *reinterpret_cast<const uint2 *>(cnt + 2 * cell);
-        return RawCount{w.x, w.y};
+        r.w0 = w.x;
+        r.w1 = w.y;
+        if constexpr (FI) {
+            const uint2 d = *reinterpret_cast<const uint2 *>(dprev + 2 * cell);
+            r.d0 = d.x;
+            r.d1 = d.y;
+        }
     }
+    return r;
 }
 
+// Counts of the cell: base plus delta in modular uint32 arithmetic; for U16
+// the packed sum equals nA + 2^16 nB whenever both true counts fit 16 bits.
 template <int CW>
 __device__ __forceinline__ uint2 counts_of(const RawCount &r)
 {
-    if constexpr (CW == COUNT_U16) return make_uint2(r.w0 & 0xFFFFu, r.w0 >> 16);
-    else return make_uint2(r.w0, r.w1);
+    if constexpr (CW == COUNT_U16) {
+        const uint32_t w = r.w0 + r.d0;
+        return make_uint2(w & 0xFFFFu, w >> 16);
+    } else {
+        return make_uint2(r.w0 + r.d0, r.w1 + r.d1);
+    }
 }
 
 // One bead of type t leaves cell `from` and enters cell `to` (non-returning
@@ -467,9 +487,9 @@ __device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0
 
 // One wave tile of the sweep: the even pass, the odd pass and the density
 // delta of up to G whole chains, from positions already loaded by tile_load.
-template <int R, int CW, class Bead>
+template <int R, int CW, bool FI, class Bead>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
-                                           uint32_t *dcur, Bead b0, Bead b1)
+                                           const uint32_t *dprev, uint32_t *dcur, Bead b0, Bead b1)
 {
     const Tile T = a.tiles[wave];
     const DevSys &S = a.systems[T.sys];
@@ -524,9 +544,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
         dw0 = t0 ? wn0.y - wo0.y : wn0.x - wo0.x;
         dw1 = t1 ? wn1.y - wo1.y : wn1.x - wo1.x;
     } else {
-        RawCount rn0{0u, 0u}, ro0{0u, 0u}, rn1{0u, 0u}, ro1{0u, 0u};
-        if (g0) { rn0 = load_raw<CW>(cin, cell_off + nc0); ro0 = load_raw<CW>(cin, cell_off + old0); }
-        if (g1) { rn1 = load_raw<CW>(cin, cell_off + nc1); ro1 = load_raw<CW>(cin, cell_off + old1); }
+        RawCount rn0{0u, 0u, 0u, 0u}, ro0{0u, 0u, 0u, 0u}, rn1{0u, 0u, 0u, 0u}, ro1{0u, 0u, 0u, 0u};
+        if (g0) {
+            rn0 = load_raw<CW, FI>(cin, dprev, cell_off + nc0);
+            ro0 = load_raw<CW, FI>(cin, dprev, cell_off + old0);
+        }
+        if (g1) {
+            rn1 = load_raw<CW, FI>(cin, dprev, cell_off + nc1);
+            ro1 = load_raw<CW, FI>(cin, dprev, cell_off + old1);
+        }
         if (g0) dw0 = omega_of(fc, counts_of<CW>(rn0), t0) - omega_of(fc, counts_of<CW>(ro0), t0);
         if (g1) dw1 = omega_of(fc, counts_of<CW>(rn1), t1) - omega_of(fc, counts_of<CW>(ro1), t1);
     }
@@ -578,13 +604,29 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
 // waves): with W = T (the default) one tile per wave; with fewer waves each
 // wave stays resident and walks its range.  One tile's state is live at a
 // time, which keeps the register count (and so the occupancy) of the
-// one-tile case.
-template <int R, int CW, bool LOOP>
+// one-tile case.  With FI every thread also folds count words of the
+// previous sweep: the first word's loads are issued before the move work
+// and its stores after it, so they overlap.
+template <int R, int CW, bool LOOP, bool FI>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
     const uint64_t s = *a.sweep_ctr + a.rel;
+    const int64_t W = a.count_words;
+    // FI: counts of sweep s are B[s-1] + D[s-1]; this sweep adds to D[s],
+    // writes B[s] and clears D[s+1] (last read by sweep s-1)
+    const uint32_t *cin = FI ? a.base + ((s + 1) & 1) * W : a.base;
+    const uint32_t *dprev = FI ? a.delta + ((s + 2) % 3) * W : nullptr;
+    uint32_t *dcur = FI ? a.delta + (s % 3) * W : a.delta;
     const int wave = wave_tile(a.waves_per_block, a.xcd_remap);
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t fb = 0u, fd = 0u;
+    if constexpr (FI) {
+        if (gtid < W) {
+            fb = cin[gtid];
+            fd = dprev[gtid];
+        }
+    }
     if constexpr (LOOP) {
         const int64_t n_waves = (int64_t)gridDim.x * a.waves_per_block;
         const int t_begin = (int)((int64_t)a.n_tiles * wave / n_waves);
@@ -592,30 +634,52 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         for (int t = t_begin; t < t_end; ++t) {
             Bead b0, b1;
             tile_load(a, t, b0, b1);
-            sweep_tile<R, CW>(a, t, s, a.counts, a.delta, b0, b1);
+            sweep_tile<R, CW, FI>(a, t, s, cin, dprev, dcur, b0, b1);
         }
     } else {
-        if (wave >= a.n_tiles) return;
-        Bead b0, b1;
-        tile_load(a, wave, b0, b1);
-        sweep_tile<R, CW>(a, wave, s, a.counts, a.delta, b0, b1);
+        if (wave < a.n_tiles) {
+            Bead b0, b1;
+            tile_load(a, wave, b0, b1);
+            sweep_tile<R, CW, FI>(a, wave, s, cin, dprev, dcur, b0, b1);
+        }
+    }
+    if constexpr (FI) {
+        uint32_t *bcur = a.base + (s & 1) * W;
+        uint32_t *dnext = a.delta + ((s + 1) % 3) * W;
+        const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+        bool ovf = false;
+        if (gtid < W) {
+            uint32_t w;
+            ovf |= fold_word<CW>(fb, fd, w);
+            bcur[gtid] = w;
+            dnext[gtid] = 0u;
+        }
+        for (int64_t i = gtid + nthreads; i < W; i += nthreads) {
+            uint32_t w;
+            ovf |= fold_word<CW>(cin[i], dprev[i], w);
+            bcur[i] = w;
+            dnext[i] = 0u;
+        }
+        if (ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
     }
 }
 
-// Fold the sweep's density delta into the counts and clear it: 16-byte
-// accesses (both arrays are 256-byte aligned), then the words past the last
-// full quadruple.
+// Fold a density delta into counts and clear it: out = in + delta (out may
+// be in), with 16-byte accesses (the arrays are 256-byte aligned), then the
+// words past the last full quadruple.
 template <int CW>
-__global__ __launch_bounds__(256) void k_fold(uint32_t *counts, uint32_t *delta, int64_t n, uint32_t *status)
+__global__ __launch_bounds__(256) void k_fold(const uint32_t *in, uint32_t *delta, uint32_t *counts, int64_t n,
+                                              uint32_t *status)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n4 = n >> 2;
+    const uint4 *i4 = reinterpret_cast<const uint4 *>(in);
     uint4 *c4 = reinterpret_cast<uint4 *>(counts);
     uint4 *d4 = reinterpret_cast<uint4 *>(delta);
     bool ovf = false;
     for (int64_t i = tid; i < n4; i += stride) {
-        const uint4 b = c4[i], d = d4[i];
+        const uint4 b = i4[i], d = d4[i];
         uint4 w;
         ovf |= fold_word<CW>(b.x, d.x, w.x);
         ovf |= fold_word<CW>(b.y, d.y, w.y);
@@ -626,7 +690,7 @@ __global__ __launch_bounds__(256) void k_fold(uint32_t *counts, uint32_t *delta,
     }
     for (int64_t i = 4 * n4 + tid; i < n; i += stride) {
         uint32_t w;
-        ovf |= fold_word<CW>(counts[i], delta[i], w);
+        ovf |= fold_word<CW>(in[i], delta[i], w);
         counts[i] = w;
         delta[i] = 0u;
     }
@@ -1065,10 +1129,14 @@ __global__ __launch_bounds__(256) void k_obs_finalize(const double *partials, in
 template <int R, int CW>
 static hipError_t launch_sweep_t(const SweepArgs &a, int blocks, hipStream_t st)
 {
-    if (a.max_blocks > 0)
-        hipLaunchKernelGGL((k_sweep<R, CW, true>), dim3(blocks), dim3(64 * a.waves_per_block), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_sweep<R, CW, false>), dim3(blocks), dim3(64 * a.waves_per_block), 0, st, a);
+    const dim3 g(blocks), b(64 * a.waves_per_block);
+    if (a.fold_in) {
+        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, true>), g, b, 0, st, a);
+    } else {
+        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, false>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, false>), g, b, 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -1117,13 +1185,16 @@ hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off
     return hipGetLastError();
 }
 
-hipError_t launch_fold(int cw, uint32_t *counts, uint32_t *delta, int64_t n, uint32_t *status, hipStream_t st)
+hipError_t launch_fold(int cw, const uint32_t *counts_in, uint32_t *delta, uint32_t *counts_out, int64_t n,
+                       uint32_t *status, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     int64_t blocks = ((n + 3) / 4 + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    if (cw == COUNT_U16) hipLaunchKernelGGL((k_fold<COUNT_U16>), dim3((unsigned)blocks), dim3(256), 0, st, counts, delta, n, status);
-    else hipLaunchKernelGGL((k_fold<COUNT_U32>), dim3((unsigned)blocks), dim3(256), 0, st, counts, delta, n, status);
+    if (cw == COUNT_U16)
+        hipLaunchKernelGGL((k_fold<COUNT_U16>), dim3((unsigned)blocks), dim3(256), 0, st, counts_in, delta, counts_out, n, status);
+    else
+        hipLaunchKernelGGL((k_fold<COUNT_U32>), dim3((unsigned)blocks), dim3(256), 0, st, counts_in, delta, counts_out, n, status);
     return hipGetLastError();
 }
 

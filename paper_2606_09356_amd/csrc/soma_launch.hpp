@@ -17,9 +17,11 @@ struct SweepArgs {
     const uint32_t *chain_id;      // logical chain id (within its system) per chain slot
     float *P0, *P1, *P2;           // coordinates (F32) or offsets (CELL)
     int *C0, *C1, *C2;             // cells (CELL only)
-    const uint32_t *counts;        // counts of this sweep (read only)
-    uint32_t *delta;               // density delta of this sweep (atomics)
+    uint32_t *base;                // two count buffers of count_words words each
+    uint32_t *delta;               // three delta buffers of count_words words each
     int64_t count_words;           // uint32 words per buffer
+    int fold_in;                   // 0: counts in base[0], delta in delta[0], folded by k_fold;
+                                   // 1: rotation, the sweep kernel folds the previous delta
     const float2 *omega;           // frozen fields, per cell (A, B)
     const uint64_t *sweep_ctr;     // sweeps done before this graph / launch sequence
     uint32_t rel;                  // sweep index relative to *sweep_ctr
@@ -100,7 +102,8 @@ hipError_t launch_density(int repr, int cw, const DensityArgs &a, hipStream_t st
 hipError_t launch_fields(int cw, const FieldArgs &a, hipStream_t st);
 hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off, int64_t n_cells,
                                 uint32_t *out, hipStream_t st);
-hipError_t launch_fold(int cw, uint32_t *counts, uint32_t *delta, int64_t n, uint32_t *status, hipStream_t st);
+hipError_t launch_fold(int cw, const uint32_t *counts_in, uint32_t *delta, uint32_t *counts_out, int64_t n,
+                       uint32_t *status, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_advance(uint64_t *ctr, uint32_t n, hipStream_t st);
 hipError_t launch_init(const InitArgs &a, hipStream_t st);

@@ -43,6 +43,7 @@ class soma_options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("pos_repr", C.c_int32), ("count_width", C.c_int32),
                 ("use_graph", C.c_int32), ("density_mode", C.c_int32), ("reorder_every", C.c_int32),
                 ("waves_per_block", C.c_int32), ("waves_per_cu", C.c_int32), ("sys_id_base", C.c_int32),
+                ("launch_order", C.c_int32),
                 ("hip_stream", C.c_void_p)]
 
 
@@ -62,7 +63,7 @@ class soma_info(C.Structure):
 
 class soma_tune(C.Structure):
     _fields_ = [("waves_per_block", C.c_int32), ("waves_per_cu", C.c_int32), ("xcd_remap", C.c_int32),
-                ("n_candidates", C.c_int32), ("us_per_sweep", C.c_double),
+                ("density_mode", C.c_int32), ("n_candidates", C.c_int32), ("us_per_sweep", C.c_double),
                 ("us_per_sweep_before", C.c_double)]
 
 
@@ -139,7 +140,7 @@ class Soma:
     def __init__(self, systems: Sequence[SystemDesc], seed: int = 0, pos_repr: str = "f32",
                  count_width: int = 16, use_graph: bool = True, density_mode: int = 0,
                  reorder_every: int = 0, waves_per_block: int = 0, waves_per_cu: int = 0,
-                 sys_id_base: int = 0,
+                 sys_id_base: int = 0, launch_order: int = 0,
                  device: str = "cuda:0", stream=None):
         import torch
         self._torch = torch
@@ -159,6 +160,7 @@ class Soma:
         o.waves_per_block = waves_per_block
         o.waves_per_cu = waves_per_cu
         o.sys_id_base = sys_id_base
+        o.launch_order = launch_order
         o.hip_stream = self.stream.cuda_stream
         self.options = o
         self.pos_repr = o.pos_repr

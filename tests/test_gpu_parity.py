@@ -188,18 +188,23 @@ def test_gpu_init_matches_oracle_walks(r):
 def test_graph_tiling_and_xcd_invariance():
     systems = W.batched_mixed(n_systems=6, seed=46, bead_range=(2000, 15000))
     ref = None
-    for use_graph, wpb, wpcu, reorder in [(False, 1, 0, 0), (True, 4, 0, 0), (True, 16, 0, 0), (False, 7, 0, 0),
-                                          (True, 4, 1, 0), (True, 2, 8, 0), (True, 4, 0, 1), (False, 4, 0, 2),
-                                          (True, 4, 0, 3)]:
+    for use_graph, wpb, wpcu, reorder, dm in [(False, 1, 0, 0, 0), (True, 4, 0, 0, 0), (True, 16, 0, 0, 0),
+                                              (False, 7, 0, 0, 0), (True, 4, 1, 0, 0), (True, 2, 8, 0, 0),
+                                              (True, 4, 0, 1, 0), (False, 4, 0, 2, 0), (True, 4, 0, 3, 0),
+                                              (True, 4, 0, 0, 1), (False, 1, 0, 2, 1), (True, 2, 8, 3, 1),
+                                              (True, 16, 32, 0, 1)]:
         g = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, use_graph=use_graph, waves_per_block=wpb,
-                 waves_per_cu=wpcu, reorder_every=reorder)
-        g.sweep(5)
+                 waves_per_cu=wpcu, reorder_every=reorder, density_mode=dm)
+        g.sweep(2)
+        g.sweep(3)
         st = [g.state(k) for k in range(len(systems))]
+        den = [g.density(k) for k in range(len(systems))]
         if ref is None:
-            ref = st
+            ref, ref_den = st, den
         else:
-            for a, b in zip(ref, st):
-                assert (a[0] == b[0]).all() and (a[1] == b[1]).all(), (use_graph, wpb, wpcu, reorder)
+            for a, b, da, db in zip(ref, st, ref_den, den):
+                assert (a[0] == b[0]).all() and (a[1] == b[1]).all(), (use_graph, wpb, wpcu, reorder, dm)
+                assert (da == db).all(), (use_graph, wpb, wpcu, reorder, dm)
         g.close()
 
 
@@ -220,10 +225,10 @@ def test_autotune_keeps_the_trajectory(r):
     b.sweep(2)
     t = a.autotune(trial_sweeps=2)
     print(f"[autotune {r}] {t}", flush=True)
-    assert t["n_candidates"] == 30 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
+    assert t["n_candidates"] == 60 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
     i = a.info()
-    assert (i["waves_per_block"], i["waves_per_cu"], i["xcd_remap"]) == \
-        (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"])
+    assert (i["waves_per_block"], i["waves_per_cu"], i["xcd_remap"], i["density_mode"]) == \
+        (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"], t["density_mode"])
     assert i["sweep"] == 2
     a.sweep(5)
     b.sweep(5)
@@ -249,16 +254,17 @@ def test_batched_equals_each_system_alone():
     g.close()
 
 
-@pytest.mark.parametrize("r", ["f32", "cell"])
-def test_checkpoint_resume_bit_exact(r):
+@pytest.mark.parametrize("r,dm", [("f32", 0), ("cell", 0), ("f32", 1), ("cell", 1)])
+def test_checkpoint_resume_bit_exact(r, dm):
+    """A checkpoint taken in one density mode resumes bit-exactly in the other."""
     systems = W.batched_mixed(n_systems=3, seed=48, bead_range=(2000, 8000))
-    a = Soma(systems, seed=SEED, pos_repr=r, count_width=16)
+    a = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=dm)
     a.sweep(6)
-    b = Soma(systems, seed=SEED, pos_repr=r, count_width=16)
+    b = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=1 - dm)
     b.sweep(3)
     saved = [b.state(k) for k in range(len(systems))]
     b.close()
-    c = Soma(systems, seed=SEED, pos_repr=r, count_width=16)
+    c = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=dm)
     for k, st in enumerate(saved):
         if r == "f32":
             c.set_state(k, st)
