@@ -20,7 +20,8 @@
 //   * The density is updated, not rebuilt: a sweep reads the counts C
 //     (frozen, for the fields) and adds -1/+1 atomically to a delta D only
 //     for accepted moves that change cell (about 0.2 of the beads), not one
-//     atomic per bead.  Two placements of the fold C += D, D = 0:
+//     atomic per bead; a wave first merges its updates in LDS, which removes
+//     about a fifth of them.  Two placements of the fold C += D, D = 0:
 //     a short streaming kernel after each sweep, or the next sweep's own
 //     threads: sweep s then reads its counts as B[s-1] + D[s-1], writes
 //     B[s] = B[s-1] + D[s-1], adds its changes to D[s] and clears D[s+1]
@@ -348,19 +349,59 @@ __device__ __forceinline__ uint2 counts_of(const RawCount &r)
     }
 }
 
-// One bead of type t leaves cell `from` and enters cell `to` (non-returning
-// atomics; the count ranges are checked when the delta is folded).
-template <int CW>
-__device__ __forceinline__ void move_count(uint32_t *delta, int64_t from, int64_t to, int t)
+// Per-wave aggregation of the density delta in LDS before the device
+// atomics.  Device-scope atomics are executed at the memory side at a fixed
+// rate; updates of one chain often hit the same count word (a chain carries
+// a count along: one bead leaves a cell that another bead of the same chain
+// enters), so merging a wave's updates first removes about a fifth of them.
+// Open addressing over kAggSlots slots: key = word index + 1 (0 = empty).
+// A wave makes at most 4 updates per lane, 256 in all, so a slot is always
+// found and the probe loop ends.
+constexpr int kAggSlots = 256;
+
+__device__ __forceinline__ uint32_t agg_hash(uint32_t key)
 {
-    if constexpr (CW == COUNT_U16) {
-        const uint32_t inc = t ? 0x10000u : 1u;
-        __hip_atomic_fetch_add(delta + from, 0u - inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(delta + to, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        __hip_atomic_fetch_add(delta + 2 * from + t, 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(delta + 2 * to + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (__umul24(key, 0x9E3779u) >> 10) & (kAggSlots - 1);
+}
+
+__device__ __forceinline__ void agg_insert(uint32_t *keys, uint32_t *vals, uint32_t key, uint32_t v, bool on)
+{
+    uint32_t h = agg_hash(key);
+    bool pending = on;
+    while (__ballot(pending) != 0) {
+        if (pending) {
+            const uint32_t old = atomicCAS(keys + h, 0u, key);
+            if (old == 0u || old == key) {
+                atomicAdd(vals + h, v);
+                pending = false;
+            } else {
+                h = (h + 1u) & (kAggSlots - 1);
+            }
+        }
     }
+}
+
+// Empty the wave's table (each lane clears kAggSlots / 64 keys and values).
+__device__ __forceinline__ void agg_clear(uint32_t *keys, uint32_t *vals)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    for (int k = lane; k < kAggSlots; k += 64) {
+        keys[k] = 0u;
+        vals[k] = 0u;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Word index and packed increment of one bead of type t in a cell.
+template <int CW>
+__device__ __forceinline__ uint32_t count_word(int64_t cell, int t)
+{
+    return CW == COUNT_U16 ? (uint32_t)cell : (uint32_t)(2 * cell + t);
+}
+template <int CW>
+__device__ __forceinline__ uint32_t count_inc(int t)
+{
+    return CW == COUNT_U16 ? (t ? 0x10000u : 1u) : 1u;
 }
 
 // Fold one word: counts' = counts + delta in modular uint32 arithmetic (for
@@ -489,7 +530,8 @@ __device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0
 // delta of up to G whole chains, from positions already loaded by tile_load.
 template <int R, int CW, bool FI, class Bead>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
-                                           const uint32_t *dprev, uint32_t *dcur, Bead b0, Bead b1)
+                                           const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
+                                           uint32_t *agg_vals, Bead b0, Bead b1)
 {
     const Tile T = a.tiles[wave];
     const DevSys &S = a.systems[T.sys];
@@ -585,9 +627,22 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     }
     if (active) store_pair(A, slot, b0, b1);
 
-    // density delta: only beads that changed cell
-    if (acc0 && nc0 != old0) move_count<CW>(dcur, cell_off + old0, cell_off + nc0, t0);
-    if (acc1 && nc1 != old1) move_count<CW>(dcur, cell_off + old1, cell_off + nc1, t1);
+    // density delta: only beads that changed cell, merged per wave in LDS,
+    // then one device atomic per distinct word with a nonzero sum
+    {
+        const bool m0 = acc0 && nc0 != old0, m1 = acc1 && nc1 != old1;
+        const uint32_t i0 = count_inc<CW>(t0), i1 = count_inc<CW>(t1);
+        agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + old0, t0) + 1u, 0u - i0, m0);
+        agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + nc0, t0) + 1u, i0, m0);
+        agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + old1, t1) + 1u, 0u - i1, m1);
+        agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + nc1, t1) + 1u, i1, m1);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int k = lane; k < kAggSlots; k += 64) {
+            const uint32_t key = agg_keys[k], v = agg_vals[k];
+            if (key != 0u && v != 0u)
+                __hip_atomic_fetch_add(dcur + (key - 1u), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 
     const uint64_t nacc = __popcll(__ballot(acc0)) + __popcll(__ballot(acc1));
     const bool any_bad = __ballot(active && bad) != 0;
@@ -620,6 +675,10 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     uint32_t *dcur = FI ? a.delta + (s % 3) * W : a.delta;
     const int wave = wave_tile(a.waves_per_block, a.xcd_remap);
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // this wave's aggregation table (2 kAggSlots words of dynamic LDS per wave)
+    HIP_DYNAMIC_SHARED(uint32_t, agg_lds)
+    uint32_t *agg_keys = agg_lds + (threadIdx.x >> 6) * (2 * kAggSlots);
+    uint32_t *agg_vals = agg_keys + kAggSlots;
     uint32_t fb = 0u, fd = 0u;
     if constexpr (FI) {
         if (gtid < W) {
@@ -634,13 +693,15 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         for (int t = t_begin; t < t_end; ++t) {
             Bead b0, b1;
             tile_load(a, t, b0, b1);
-            sweep_tile<R, CW, FI>(a, t, s, cin, dprev, dcur, b0, b1);
+            agg_clear(agg_keys, agg_vals);
+            sweep_tile<R, CW, FI>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
         }
     } else {
         if (wave < a.n_tiles) {
             Bead b0, b1;
             tile_load(a, wave, b0, b1);
-            sweep_tile<R, CW, FI>(a, wave, s, cin, dprev, dcur, b0, b1);
+            agg_clear(agg_keys, agg_vals);
+            sweep_tile<R, CW, FI>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
         }
     }
     if constexpr (FI) {
@@ -1130,12 +1191,13 @@ template <int R, int CW>
 static hipError_t launch_sweep_t(const SweepArgs &a, int blocks, hipStream_t st)
 {
     const dim3 g(blocks), b(64 * a.waves_per_block);
+    const size_t lds = sizeof(uint32_t) * 2 * kAggSlots * a.waves_per_block;
     if (a.fold_in) {
-        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((k_sweep<R, CW, false, true>), g, b, 0, st, a);
+        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, true>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, true>), g, b, lds, st, a);
     } else {
-        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, false>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((k_sweep<R, CW, false, false>), g, b, 0, st, a);
+        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, false>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, false>), g, b, lds, st, a);
     }
     return hipGetLastError();
 }
