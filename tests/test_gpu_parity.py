@@ -35,7 +35,15 @@ def small_cases():
         "batched_uneven_small/f32/u16": (W.batched_uneven(n_systems=6, seed=41, chain_range=(60, 700)), "f32", 16),
         "batched_mixed_small/cell/u16": (W.batched_mixed(n_systems=10, seed=42, bead_range=(2000, 20000)), "cell", 16),
         "batched_mixed_small/f32/u32": (W.batched_mixed(n_systems=5, seed=43, bead_range=(3000, 9000)), "f32", 32),
+        # 16384 beads in 8 cells: every wave's density updates hit a handful of
+        # count words, the worst case for the per-wave merge of the delta
+        "crowded/f32/u16": ([crowded()], "f32", 16),
+        "crowded/cell/u32": ([crowded()], "cell", 32),
     }
+
+
+def crowded():
+    return W.diblock_system(512, 32, 0.5, 20.0, 50.0, (0.5, 0.5, 0.5), (2, 2, 2), "crowded")
 
 
 def make_pair(systems, pos_repr, cw, pos_seed=7, **kw):
