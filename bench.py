@@ -217,6 +217,8 @@ def main():
     systems, info, sec, wall, obs = run_workload(args.workload, args.steps, args.warmup, shape, autotune)
     B = info["n_beads"]
     prof = profiled(args.workload)
+    if prof and prof.get("density_mode") != info["density_mode"]:
+        prof = None         # profiled with the other fold placement
     moves_per_s = B * args.steps / sec
     ms_per_step = sec * 1e3 / args.steps
     achieved = info["bytes_per_sweep"] / (sec / args.steps) / 1e9
@@ -241,8 +243,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": prof["traffic_bytes_per_launch"] if prof else None,
                      "bytes_per_sweep": info["bytes_per_sweep"],
-                     "kernel": "k_sweep + k_fold (move with fields from the counts; density delta "
-                               "folded into the counts), one pair of launches per sweep",
+                     "kernel": ("k_sweep (moves with fields from base + previous delta, folds the previous "
+                                "delta), one launch per sweep" if info["density_mode"] == 1 else
+                                "k_sweep + k_fold (moves with fields from the counts, then the delta fold), "
+                                "two launches per sweep"),
                      "avg_sweep_us_hip_events": sec / args.steps * 1e6},
         "observables": {k: obs[k] for k in ("Re2", "Re2_err", "Rg2", "Ebond_per_chain", "Enb_per_chain",
                                            "accept_ratio")},
