@@ -39,7 +39,15 @@ def small_cases():
         # count words, the worst case for the per-wave merge of the delta
         "crowded/f32/u16": ([crowded()], "f32", 16),
         "crowded/cell/u32": ([crowded()], "cell", 32),
+        # cell edge just above the move half-width: almost every accepted move
+        # changes cell, so a wave's merge table holds up to 256 distinct words
+        "fine_grid/f32/u16": ([fine_grid()], "f32", 16),
+        "fine_grid/cell/u16": ([fine_grid()], "cell", 16),
     }
+
+
+def fine_grid():
+    return W.diblock_system(1024, 32, 0.5, 20.0, 50.0, (1.275, 1.275, 1.275), (25, 25, 25), "fine_grid")
 
 
 def crowded():
