@@ -38,7 +38,7 @@ class _System(C.Structure):
                 ("ham_form", C.c_int32), ("pattern_a", C.c_void_p), ("pattern_b", C.c_void_p),
                 ("chiN", C.c_double), ("kappaN", C.c_double), ("Re", C.c_double),
                 ("box", C.c_double * 3), ("grid", C.c_int32 * 3),
-                ("move_halfwidth", C.c_double), ("sys_id", C.c_uint32)]
+                ("move_halfwidth", C.c_double), ("sys_id", C.c_uint32), ("smc_A", C.c_double)]
 
 
 class _State(C.Structure):
@@ -76,6 +76,8 @@ def lib():
         L.orc_observables.argtypes = [P, P, P, P, P]
         L.orc_neumaier_sum.argtypes = [P, C.c_int64]
         L.orc_neumaier_sum.restype = C.c_double
+        L.orc_smc_draw.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, P, P]
+        L.orc_smc_draw.restype = None
         _lib = L
     return _lib
 
@@ -97,6 +99,14 @@ def neumaier_sum(v) -> float:
     return lib().orc_neumaier_sum(_ptr(a), a.size)
 
 
+def smc_draw(seed: int, sweep: int, chain: int, bead: int, sys_id: int = 0):
+    """The three standard normals and the acceptance variate of one smart move."""
+    xi = np.zeros(3)
+    u = C.c_double(0.0)
+    lib().orc_smc_draw(seed, sweep, chain, bead, sys_id, _ptr(xi), C.byref(u))
+    return xi, u.value
+
+
 class OracleSystem:
     """One system of the oracle: its description, stored positions, counts and fields."""
 
@@ -113,6 +123,7 @@ class OracleSystem:
         s.box = (C.c_double * 3)(*desc.box)
         s.grid = (C.c_int32 * 3)(*desc.grid)
         s.move_halfwidth = desc.move_halfwidth
+        s.smc_A = float(getattr(desc, "smc_A", 0.0))
         s.sys_id = sys_id
         self._sys = s
         B, M = desc.n_beads, desc.n_cells

@@ -25,7 +25,13 @@
  *     phi_t      n_t(c) * M / B (mean of phiA+phiB is one)
  *     omega_t    dH_nb/dn_t(c)
  *     moves      uniform in a cube of half-width delta, Metropolis, even
- *                beads first, then odd beads, fields frozen for the sweep
+ *                beads first, then odd beads, fields frozen for the sweep;
+ *                or, when smc_A > 0, bond-force-biased ("smart") moves
+ *                (Sec. 2 names them as SOMA's move; Rossky, Doll and
+ *                Friedman, J. Chem. Phys. 69, 4628 (1978)): displacement
+ *                A F + sqrt(2A) xi with F the bond force and xi standard
+ *                normal, accepted with the Metropolis-Hastings ratio of the
+ *                Gaussian proposal densities
  *     density    nearest-grid-point, cell = floor(x / cell edge) mod n
  *     RNG        Philox4x32-10 keyed by (seed) with counter
  *                (bead, chain, sweep, system)
@@ -92,6 +98,7 @@ typedef struct {
     int32_t grid[3];
     double move_halfwidth;
     uint32_t sys_id;
+    double smc_A;             /* > 0: smart moves with this A (Re^2); 0: uniform moves */
 } orc_system;
 
 typedef struct {
@@ -279,6 +286,34 @@ static void move_draw(const orc_system *s, uint64_t seed, uint32_t sweep, int64_
     *u = (double)((float)(w[3] >> 8) * 0x1p-24f);
 }
 
+/* Random numbers of one smart move: three standard normals by Box-Muller on
+ * the block with counter (bead, chain, sweep, system) -- words 0 and 1 give
+ * the first two, words 2 and 3 the third -- and the acceptance variate from
+ * word 0 of the block with counter (bead + 256, chain, sweep, system).  Beads
+ * are numbered below 128, so the second block never meets a first one.
+ * The uniforms of Box-Muller are ((w >> 8) + 1/2) 2^-24 (never zero, for the
+ * logarithm) and (w >> 8) 2^-24, as in the initial walks. */
+void orc_smc_draw(uint64_t seed, uint32_t sweep, uint32_t chain, uint32_t i, uint32_t sys_id,
+                  double xi[3], double *u)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {i, chain, sweep, sys_id};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    double u1 = ((double)(w[0] >> 8) + 0.5) * 0x1p-24;
+    double u2 = (double)(w[1] >> 8) * 0x1p-24;
+    double u3 = ((double)(w[2] >> 8) + 0.5) * 0x1p-24;
+    double u4 = (double)(w[3] >> 8) * 0x1p-24;
+    double rad1 = sqrt(-2.0 * log(u1)), rad2 = sqrt(-2.0 * log(u3));
+    xi[0] = rad1 * cos(two_pi * u2);
+    xi[1] = rad1 * sin(two_pi * u2);
+    xi[2] = rad2 * cos(two_pi * u4);
+    uint32_t ctr2[4] = {i + 256u, chain, sweep, sys_id};
+    orc_philox4x32_10(ctr2, key, w);
+    *u = (double)((float)(w[0] >> 8) * 0x1p-24f);
+}
+
 /* ------------------------------------------------------------------------ */
 /* One MC sweep with frozen fields                                           */
 /* ------------------------------------------------------------------------ */
@@ -299,7 +334,38 @@ uint64_t orc_sweep(const orc_system *s, orc_state *st, uint64_t seed, uint32_t s
                 int64_t b = c * N + i;
                 float d[3];
                 double u;
-                move_draw(s, seed, sweep, c, i, d, &u);
+                /* smart move: bond force at the current position (the
+                 * neighbours hold still during this bead's move) */
+                double F[3] = {0.0, 0.0, 0.0};
+                int n_nb = 0;
+                int smart = s->smc_A > 0.0;
+                if (smart) {
+                    double xi[3];
+                    orc_smc_draw(seed, sweep, (uint32_t)c, (uint32_t)i, s->sys_id, xi, &u);
+                    double sum[3] = {0.0, 0.0, 0.0};
+                    for (int side = -1; side <= 1; side += 2) {
+                        int j = i + side;
+                        if (j < 0 || j >= N) continue;
+                        ++n_nb;
+                        for (int a = 0; a < 3; ++a)
+                            sum[a] += get_pos(s, st, a, c * N + j) - get_pos(s, st, a, b);
+                    }
+                    int inside = 1;
+                    for (int a = 0; a < 3; ++a) {
+                        F[a] = k * sum[a];
+                        d[a] = (float)(s->smc_A * F[a] + sqrt(2.0 * s->smc_A) * xi[a]);
+                        /* displacements of 0.99 cell edges or more are
+                         * rejected outright: a condition symmetric in r and
+                         * r', so the chain keeps detailed balance */
+                        if (!(fabsf(d[a]) < (float)(0.99 * cell_edge(s, a)))) inside = 0;
+                    }
+                    if (!inside) {
+                        if (accepted) accepted[b] = 0;
+                        continue;
+                    }
+                } else {
+                    move_draw(s, seed, sweep, c, i, d, &u);
+                }
 
                 /* Old and proposed position in FP64, proposed state stored
                  * in the mode's representation. */
@@ -354,6 +420,18 @@ uint64_t orc_sweep(const orc_system *s, orc_state *st, uint64_t seed, uint32_t s
                 }
                 int64_t cell_new = (idx[0] * s->grid[1] + idx[1]) * s->grid[2] + idx[2];
                 dE += omega[(int64_t)t * M + cell_new] - omega[(int64_t)t * M + cell_old];
+                if (smart) {
+                    /* log of q(r'->r)/q(r->r') for the Gaussian proposal
+                     * q(r->r') ~ exp(-|r'-r-A F(r)|^2/(4A)); F(r') = F(r) - k n_nb d */
+                    double A = s->smc_A, fwd = 0.0, rev = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        double f = de[a] - A * F[a];
+                        double r = de[a] + A * (F[a] - k * (double)n_nb * de[a]);
+                        fwd += f * f;
+                        rev += r * r;
+                    }
+                    dE -= (fwd - rev) / (4.0 * A);
+                }
 
                 int acc = u < exp(-dE);
                 if (accepted) accepted[b] = (uint8_t)acc;

@@ -56,6 +56,7 @@ class SystemDesc:
     move_halfwidth: float = 0.05   # half-width of the uniform trial cube, in Re
     ham_form: int = 0              # 0: Helfand form, 1: chiN*phiA*phiB form
     label: str = ""
+    smc_A: float = 0.0             # > 0: bond-force-biased moves with this A (Re^2); 0: uniform moves
 
     @property
     def n_beads(self) -> int:
