@@ -15,6 +15,8 @@ Extra legs (on by default, --no-extra to skip):
             error is matched exactly, and the JSON says so.
   mixed     262144 chains, N=64 (16.8M beads), int32 cell + FP32 offset,
             uint32 counts.
+  batched mixed  256 systems (124.6M beads), cell + offset, uint16 counts.
+  smart     the default workload with bond-force-biased moves.
 The CPU baseline is the FP64 oracle (test infrastructure), timed on a
 bounded sample of the default workload on the host cores.
 
@@ -285,6 +287,15 @@ def main():
                                 "frac": binfo["bytes_per_sweep"] * bst / bsec / 1e9 / HBM_PEAK_GBS,
                                 "beads": binfo["n_beads"], "systems": len(bs), "launch_shape": shape_of(binfo),
                                 "over_plain_large": (binfo["n_beads"] * bst / bsec) / moves_per_s}
+        print("[bench] smart-move workload", flush=True)
+        ss, sinfo, ssec, _, sobs = run_workload("plain_large_smc", min(args.steps, 200), min(args.warmup, 20),
+                                                autotune=autotune)
+        sst = min(args.steps, 200)
+        out["plain_large_smc"] = {"workload": "plain_large with bond-force-biased (smart) moves, A = 4e-4 Re^2",
+                                  "moves_per_s": sinfo["n_beads"] * sst / ssec,
+                                  "hbm_gbs": sinfo["bytes_per_sweep"] * sst / ssec / 1e9,
+                                  "accept_ratio": sobs["accept_ratio"], "Re2": sobs["Re2"],
+                                  "launch_shape": shape_of(sinfo)}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)

@@ -89,6 +89,12 @@ typedef struct {
     double box[3];             /* periodic box, Re units */
     int32_t grid[3];           /* cells per direction */
     double move_halfwidth;     /* delta, Re units */
+    double smc_A;              /* 0: uniform trial moves in the cube of half-width delta.
+                                  > 0: bond-force-biased ("smart") moves, Sec. 2: displacement
+                                  A F + sqrt(2A) xi (F the bond force in kT/Re, xi standard
+                                  normal), accepted with the Metropolis-Hastings ratio of the
+                                  Gaussian proposal densities; a displacement of 0.99 cell edges
+                                  or more is rejected.  Requires sqrt(2A) <= 0.5 cell edge. */
 } soma_system_desc;
 
 typedef struct {

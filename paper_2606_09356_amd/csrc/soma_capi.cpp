@@ -59,6 +59,7 @@ struct soma_ctx {
     // before sweep s); `rot` says the buffers are in that layout.  Otherwise
     // (canonical) the counts are base[0] and every delta is zero.
     bool rot = false;
+    int any_smc = 0;       // some system moves with bond-force-biased moves
     uint64_t sweep = 0;
     uint64_t last_reorder = ~uint64_t(0);
     int latched = SOMA_OK;
@@ -147,6 +148,8 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
             const double edge = d.box[a] / d.grid[a];
             if (!(d.move_halfwidth > 0) || !(d.move_halfwidth < 0.99 * edge))
                 return bad("move_halfwidth must be in (0, 0.99 cell edge)");
+            if (!(d.smc_A >= 0) || !std::isfinite(d.smc_A) || std::sqrt(2.0 * d.smc_A) > 0.5 * edge)
+                return bad("smc_A must be 0 or positive with sqrt(2 smc_A) <= 0.5 cell edge");
         }
         if (cells >= (int64_t(1) << 31)) return bad("too many cells");
         if ((int64_t)d.grid[0] * d.grid[1] > (int64_t(1) << 24)) return bad("grid[0] * grid[1] must be <= 2^24");
@@ -194,6 +197,14 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
             }
             const double k_spring = 3.0 * (d.N - 1) / (d.Re * d.Re);
             v.k_half = (float)(0.5 * k_spring);
+            v.smc = d.smc_A > 0 ? 1 : 0;
+            v.smc_A = d.smc_A;
+            v.smc_s2A = std::sqrt(2.0 * d.smc_A);
+            v.k_spring = k_spring;
+            v.smc_Af = (float)d.smc_A;
+            v.smc_inv4A = d.smc_A > 0 ? (float)(1.0 / (4.0 * d.smc_A)) : 0.0f;
+            v.k_f = (float)k_spring;
+            for (int a = 0; a < 3; ++a) v.dmax[a] = (float)(0.99 * (d.box[a] / d.grid[a]));
             v.delta = (float)d.move_halfwidth;
             v.inv_P = (float)(1.0 / P);
             const double s = (double)M / ((double)d.n_chains * d.N);   // phi per count
@@ -324,6 +335,7 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
     a.delta = c->delta(0);
     a.count_words = c->L.count_words;
     a.fold_in = c->density_mode;
+    a.smc = c->any_smc;
     a.omega = c->omega();
     a.sweep_ctr = c->sweep_ctr();
     a.rel = rel;
@@ -599,6 +611,7 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
     c->density_mode = opt->density_mode;
     c->stream = reinterpret_cast<hipStream_t>(opt->hip_stream);
     c->L = plan(sys, n_sys, opt, &c->sys);
+    for (const HostSys &h : c->sys) c->any_smc |= h.dev.smc;
     if (workspace_bytes < c->L.total) {
         char b[128];
         std::snprintf(b, sizeof b, "workspace has %zu bytes, needs %zu", workspace_bytes, c->L.total);

@@ -529,6 +529,38 @@ __device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0
 
 // One wave tile of the sweep: the even pass, the odd pass and the density
 // delta of up to G whole chains, from positions already loaded by tile_load.
+// End of a wave tile: the density delta of the beads that changed cell,
+// merged per wave in LDS, then one device atomic per distinct word with a
+// nonzero sum; the acceptance count and the cell-range status.
+template <int CW>
+__device__ __forceinline__ void tile_finish(const SweepArgs &a, int wave, uint32_t sys, int64_t cell_off,
+                                            uint32_t *dcur, uint32_t *agg_keys, uint32_t *agg_vals,
+                                            bool m0, int old0, int nc0, int t0, bool m1, int old1, int nc1,
+                                            int t1, bool acc0, bool acc1, bool bad)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const uint32_t i0 = count_inc<CW>(t0), i1 = count_inc<CW>(t1);
+    agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + old0, t0) + 1u, 0u - i0, m0);
+    agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + nc0, t0) + 1u, i0, m0);
+    agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + old1, t1) + 1u, 0u - i1, m1);
+    agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + nc1, t1) + 1u, i1, m1);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int k = lane; k < kAggSlots; k += 64) {
+        const uint32_t key = agg_keys[k], v = agg_vals[k];
+        if (key != 0u && v != 0u)
+            __hip_atomic_fetch_add(dcur + (key - 1u), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    const uint64_t nacc = __popcll(__ballot(acc0)) + __popcll(__ballot(acc1));
+    const bool any_bad = __ballot(bad) != 0;
+    if (lane == 0) {
+        if (nacc)
+            atomicAdd(a.accept + ((int64_t)sys * kAcceptSlots + (wave % kAcceptSlots)) * kAcceptStride,
+                      (unsigned long long)nacc);
+        if (any_bad) atomicOr(a.status, ST_CELL_OVERFLOW);
+    }
+}
+
 template <int R, int CW, bool FI, class Bead>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                            const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
@@ -627,32 +659,197 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
         if (acc1) b1 = n1;
     }
     if (active) store_pair(A, slot, b0, b1);
+    tile_finish<CW>(a, wave, T.sys, cell_off, dcur, agg_keys, agg_vals, acc0 && nc0 != old0, old0, nc0, t0,
+                    acc1 && nc1 != old1, old1, nc1, t1, acc0, acc1, active && bad);
+}
 
-    // density delta: only beads that changed cell, merged per wave in LDS,
-    // then one device atomic per distinct word with a nonzero sum
-    {
-        const bool m0 = acc0 && nc0 != old0, m1 = acc1 && nc1 != old1;
-        const uint32_t i0 = count_inc<CW>(t0), i1 = count_inc<CW>(t1);
-        agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + old0, t0) + 1u, 0u - i0, m0);
-        agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + nc0, t0) + 1u, i0, m0);
-        agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + old1, t1) + 1u, 0u - i1, m1);
-        agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + nc1, t1) + 1u, i1, m1);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int k = lane; k < kAggSlots; k += 64) {
-            const uint32_t key = agg_keys[k], v = agg_vals[k];
-            if (key != 0u && v != 0u)
-                __hip_atomic_fetch_add(dcur + (key - 1u), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// ---------------------------------------------------------------------------
+// Bond-force-biased ("smart") moves (Sec. 2; Rossky, Doll and Friedman 1978)
+// ---------------------------------------------------------------------------
+// Three standard normals by Box-Muller (FP64) on the Philox block with counter
+// (bead, chain, sweep, system): words 0, 1 give the first two, words 2, 3 the
+// third; the acceptance variate is word 0 of the block with counter
+// (bead + 256, chain, sweep, system) (beads are numbered below 128).
+__device__ __forceinline__ void smc_draw(uint32_t bead, uint32_t chain, uint32_t sweep, uint32_t sys,
+                                         uint32_t k0, uint32_t k1, double xi[3], float &u)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    const uint4 w = philox4x32_10(make_uint4(bead, chain, sweep, sys), k0, k1);
+    const double u1 = ((double)(w.x >> 8) + 0.5) * 0x1p-24;
+    const double u2 = (double)(w.y >> 8) * 0x1p-24;
+    const double u3 = ((double)(w.z >> 8) + 0.5) * 0x1p-24;
+    const double u4 = (double)(w.w >> 8) * 0x1p-24;
+    const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
+    xi[0] = r1 * cos(two_pi * u2);
+    xi[1] = r1 * sin(two_pi * u2);
+    xi[2] = r2 * cos(two_pi * u4);
+    const uint4 w2 = philox4x32_10(make_uint4(bead + 256u, chain, sweep, sys), k0, k1);
+    u = (float)(w2.x >> 8) * 0x1p-24f;
+}
+
+// Position in FP64 from the stored representation (exact for FP32; cell
+// mode: cell * edge + offset with the FP32 edge).
+__device__ __forceinline__ double3 pos64(const BeadF32 &a, const SysView &)
+{
+    return make_double3((double)a.x, (double)a.y, (double)a.z);
+}
+__device__ __forceinline__ double3 pos64(const BeadCell &a, const SysView &v)
+{
+    return make_double3((double)a.cx * (double)v.e0 + (double)a.ox, (double)a.cy * (double)v.e1 + (double)a.oy,
+                        (double)a.cz * (double)v.e2 + (double)a.oz);
+}
+
+// One smart move of bead b with neighbours nl (if hl) and nr (if hr), which
+// hold still.  Returns the trial state and whether the displacement stays
+// below 0.99 cell edges; F gets the bond force at b (FP64).
+template <class Bead>
+__device__ __forceinline__ Bead smc_propose(const Bead &b, const Bead &nl, bool hl, const Bead &nr, bool hr,
+                                            const DevSys &S, const SysView &v, const double xi[3], double3 &F,
+                                            bool &inside)
+{
+    const double3 r = pos64(b, v);
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (hl) {
+        const double3 q = pos64(nl, v);
+        fx += q.x - r.x; fy += q.y - r.y; fz += q.z - r.z;
+    }
+    if (hr) {
+        const double3 q = pos64(nr, v);
+        fx += q.x - r.x; fy += q.y - r.y; fz += q.z - r.z;
+    }
+    F = make_double3(S.k_spring * fx, S.k_spring * fy, S.k_spring * fz);
+    Draw d;
+    d.dx = (float)(S.smc_A * F.x + S.smc_s2A * xi[0]);
+    d.dy = (float)(S.smc_A * F.y + S.smc_s2A * xi[1]);
+    d.dz = (float)(S.smc_A * F.z + S.smc_s2A * xi[2]);
+    d.u = 0.0f;
+    // a displacement of 0.99 cell edges or more is rejected: the condition is
+    // symmetric in r and r', so detailed balance holds, and a kept trial move
+    // changes each cell index by at most one
+    inside = fabsf(d.dx) < S.dmax[0] && fabsf(d.dy) < S.dmax[1] && fabsf(d.dz) < S.dmax[2];
+    if (!inside) d.dx = d.dy = d.dz = 0.0f;
+    return propose(b, d, v);
+}
+
+// log of q(r'->r) / q(r->r') for q(r->r') ~ exp(-|r'-r-A F(r)|^2 / (4A)),
+// with de the stored displacement and F(r') = F(r) - k n_nb de (FP32).
+__device__ __forceinline__ float smc_log_ratio(const DevSys &S, float3 de, double3 F, int n_nb)
+{
+    const float A = S.smc_Af, kn = S.k_f * (float)n_nb;
+    const float fx = (float)F.x, fy = (float)F.y, fz = (float)F.z;
+    const float3 f = make_float3(de.x - A * fx, de.y - A * fy, de.z - A * fz);
+    const float3 r = make_float3(de.x + A * (fx - kn * de.x), de.y + A * (fy - kn * de.y), de.z + A * (fz - kn * de.z));
+    return (dot3(f, f) - dot3(r, r)) * S.smc_inv4A;
+}
+
+// Field difference between a trial cell and the old cell of one bead.
+template <int CW, bool FI>
+__device__ __forceinline__ float field_step(const SweepArgs &a, bool frozen, const FieldCoef &fc,
+                                            const uint32_t *cin, const uint32_t *dprev, int64_t cell_off,
+                                            int nc, int old, int t, bool gather)
+{
+    float dw = 0.0f;
+    if (frozen) {
+        float2 wn{0.f, 0.f}, wo{0.f, 0.f};
+        if (gather) { wn = a.omega[cell_off + nc]; wo = a.omega[cell_off + old]; }
+        dw = t ? wn.y - wo.y : wn.x - wo.x;
+    } else {
+        RawCount rn{0u, 0u, 0u, 0u}, ro{0u, 0u, 0u, 0u};
+        if (gather) {
+            rn = load_raw<CW, FI>(cin, dprev, cell_off + nc);
+            ro = load_raw<CW, FI>(cin, dprev, cell_off + old);
+            dw = omega_of(fc, counts_of<CW>(rn), t) - omega_of(fc, counts_of<CW>(ro), t);
         }
     }
+    return dw;
+}
 
-    const uint64_t nacc = __popcll(__ballot(acc0)) + __popcll(__ballot(acc1));
-    const bool any_bad = __ballot(active && bad) != 0;
-    if (lane == 0) {
-        if (nacc)
-            atomicAdd(a.accept + ((int64_t)T.sys * kAcceptSlots + (wave % kAcceptSlots)) * kAcceptStride,
-                      (unsigned long long)nacc);
-        if (any_bad) atomicOr(a.status, ST_CELL_OVERFLOW);
+// One wave tile with smart moves.  The odd bead's proposal depends on the
+// even pass (its bond force uses the moved even beads), so the two passes
+// gather their fields one after the other.
+template <int R, int CW, bool FI, class Bead>
+__device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
+                                               const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
+                                               uint32_t *agg_vals, Bead b0, Bead b1)
+{
+    const Tile T = a.tiles[wave];
+    const DevSys &S = a.systems[T.sys];
+    const SysView v = make_view(S);
+    const FieldCoef fc{S.cAA, S.cAB, S.cBA, S.cBB, S.c0};
+    const bool frozen = S.frozen != 0;
+    const int64_t cell_off = S.cell_off;
+    const int N = S.N, P = S.P;
+    const int lane = (int)(threadIdx.x & 63);
+    const int g = (int)(((float)lane + 0.5f) * S.inv_P);
+    const int p = lane - g * P;
+    const int nin = min(S.G, S.n_chains - (int)T.chain0);
+    const bool active = g < nin;
+    const int chain = (int)T.chain0 + (active ? g : 0);
+    const int i0 = 2 * p, i1 = 2 * p + 1;
+    const bool has1 = active && i1 < N;
+    const int64_t slot = S.slot_off + (int64_t)chain * (2 * P) + i0;
+    const PosArrays A{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2};
+    const uint32_t clog = a.chain_id[S.chain_off + chain];
+    const int t0 = pattern_type(S, (int)clog, i0);
+    const int t1 = pattern_type(S, (int)clog, i1 < N ? i1 : i0);
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const float kh = S.k_half;
+    bool bad = false;
+    const CellPos c0 = locate(b0, v, bad);
+    const CellPos c1 = locate(b1, v, bad);
+    const int old0 = lin(c0, v);
+    const int old1 = lin(c1, v);
+
+    // even pass: bead 2p, neighbours 2p-1 (previous lane's odd bead) and 2p+1
+    bool acc0;
+    int nc0;
+    {
+        double xi[3];
+        float u;
+        smc_draw((uint32_t)i0, clog, (uint32_t)s, S.sys_id, k0, k1, xi, u);
+        const Bead left = shfl_up1(b1);
+        const bool hl = p > 0, hr = i1 < N;
+        double3 F;
+        bool inside;
+        const Bead n0 = smc_propose(b0, left, hl, b1, hr, S, v, xi, F, inside);
+        nc0 = lin(step(c0, b0, n0, v), v);
+        const float dw = field_step<CW, FI>(a, frozen, fc, cin, dprev, cell_off, nc0, old0, t0,
+                                            active && inside && nc0 != old0);
+        const float3 de = bond(n0, b0, v);
+        const float dd = dot3(de, de);
+        float dE = 0.0f;
+        if (hl) dE += 2.0f * dot3(de, bond(b0, left, v)) + dd;
+        if (hr) dE += 2.0f * dot3(de, bond(b0, b1, v)) + dd;
+        dE = dE * kh + dw - smc_log_ratio(S, de, F, (hl ? 1 : 0) + (hr ? 1 : 0));
+        acc0 = active && inside && (u < __expf(-dE));
+        if (acc0) b0 = n0;
     }
+    // odd pass: bead 2p+1, neighbours 2p (this lane, moved) and 2p+2 (next lane)
+    bool acc1;
+    int nc1;
+    {
+        double xi[3];
+        float u;
+        smc_draw((uint32_t)i1, clog, (uint32_t)s, S.sys_id, k0, k1, xi, u);
+        const Bead right = shfl_down1(b0);
+        const bool hr = i1 + 1 < N;
+        double3 F;
+        bool inside;
+        const Bead n1 = smc_propose(b1, b0, true, right, hr, S, v, xi, F, inside);
+        nc1 = lin(step(c1, b1, n1, v), v);
+        const float dw = field_step<CW, FI>(a, frozen, fc, cin, dprev, cell_off, nc1, old1, t1,
+                                            has1 && inside && nc1 != old1);
+        const float3 de = bond(n1, b1, v);
+        const float dd = dot3(de, de);
+        float dE = 2.0f * dot3(de, bond(b1, b0, v)) + dd;
+        if (hr) dE += 2.0f * dot3(de, bond(b1, right, v)) + dd;
+        dE = dE * kh + dw - smc_log_ratio(S, de, F, 1 + (hr ? 1 : 0));
+        acc1 = has1 && inside && (u < __expf(-dE));
+        if (acc1) b1 = n1;
+    }
+    if (active) store_pair(A, slot, b0, b1);
+    tile_finish<CW>(a, wave, T.sys, cell_off, dcur, agg_keys, agg_vals, acc0 && nc0 != old0, old0, nc0, t0,
+                    acc1 && nc1 != old1, old1, nc1, t1, acc0, acc1, active && bad);
 }
 
 // The sweep kernel: one launch per sweep for every system.  Wave w of the
@@ -663,7 +860,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
 // one-tile case.  With FI every thread also folds count words of the
 // previous sweep: the first word's loads are issued before the move work
 // and its stores after it, so they overlap.
-template <int R, int CW, bool LOOP, bool FI>
+template <int R, int CW, bool LOOP, bool FI, bool SMC>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
@@ -695,14 +892,20 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
             Bead b0, b1;
             tile_load(a, t, b0, b1);
             agg_clear(agg_keys, agg_vals);
-            sweep_tile<R, CW, FI>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+            if (SMC && a.systems[a.tiles[t].sys].smc)
+                sweep_tile_smc<R, CW, FI>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+            else
+                sweep_tile<R, CW, FI>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
         }
     } else {
         if (wave < a.n_tiles) {
             Bead b0, b1;
             tile_load(a, wave, b0, b1);
             agg_clear(agg_keys, agg_vals);
-            sweep_tile<R, CW, FI>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+            if (SMC && a.systems[a.tiles[wave].sys].smc)
+                sweep_tile_smc<R, CW, FI>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+            else
+                sweep_tile<R, CW, FI>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
         }
     }
     if constexpr (FI) {
@@ -1188,19 +1391,27 @@ __global__ __launch_bounds__(256) void k_obs_finalize(const double *partials, in
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int R, int CW>
-static hipError_t launch_sweep_t(const SweepArgs &a, int blocks, hipStream_t st)
+template <int R, int CW, bool SMC>
+static hipError_t launch_sweep_s(const SweepArgs &a, int blocks, hipStream_t st)
 {
     const dim3 g(blocks), b(64 * a.waves_per_block);
     const size_t lds = sizeof(uint32_t) * 2 * kAggSlots * a.waves_per_block;
     if (a.fold_in) {
-        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, true>), g, b, lds, st, a);
-        else hipLaunchKernelGGL((k_sweep<R, CW, false, true>), g, b, lds, st, a);
+        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, true, SMC>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, true, SMC>), g, b, lds, st, a);
     } else {
-        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, false>), g, b, lds, st, a);
-        else hipLaunchKernelGGL((k_sweep<R, CW, false, false>), g, b, lds, st, a);
+        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, false, SMC>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, false, SMC>), g, b, lds, st, a);
     }
     return hipGetLastError();
+}
+
+// Contexts with smart moves use the kernels that carry both move kinds (the
+// kind is chosen per wave tile); the others keep the smaller uniform-only ones.
+template <int R, int CW>
+static hipError_t launch_sweep_t(const SweepArgs &a, int blocks, hipStream_t st)
+{
+    return a.smc ? launch_sweep_s<R, CW, true>(a, blocks, st) : launch_sweep_s<R, CW, false>(a, blocks, st);
 }
 
 hipError_t launch_sweep(int repr, int cw, const SweepArgs &a, hipStream_t st)

@@ -22,6 +22,7 @@ struct SweepArgs {
     int64_t count_words;           // uint32 words per buffer
     int fold_in;                   // 0: counts in base[0], delta in delta[0], folded by k_fold;
                                    // 1: rotation, the sweep kernel folds the previous delta
+    int smc;                       // some system uses bond-force-biased moves
     const float2 *omega;           // frozen fields, per cell (A, B)
     const uint64_t *sweep_ctr;     // sweeps done before this graph / launch sequence
     uint32_t rel;                  // sweep index relative to *sweep_ctr

@@ -49,6 +49,16 @@ struct alignas(16) DevSys {
     // omega_A = cAA nA + cAB nB + c0, omega_B = cBA nA + cBB nB + c0
     float cAA, cAB, cBA, cBB, c0;
     int64_t n_cells;
+    // bond-force-biased moves (smc != 0): displacement A F + sqrt(2A) xi in
+    // FP64, rejected at 0.99 cell edges; the acceptance ratio in FP32
+    int32_t smc;
+    float smc_Af;          // A
+    float smc_inv4A;       // 1 / (4 A)
+    float k_f;             // k = 3(N-1)/Re^2
+    float dmax[3];         // 0.99 cell edge
+    double smc_A;          // A
+    double smc_s2A;        // sqrt(2 A)
+    double k_spring;       // k in FP64 (the force of the proposal)
     alignas(16) uint32_t pat_a[kPatternWords];   // bit i: type of bead i (0 = A, 1 = B)
     alignas(16) uint32_t pat_b[kPatternWords];
 };

@@ -36,7 +36,8 @@ class soma_system_desc(C.Structure):
     _fields_ = [("n_chains", C.c_int32), ("N", C.c_int32), ("n_chains_a", C.c_int32),
                 ("ham_form", C.c_int32), ("pattern_a", C.c_void_p), ("pattern_b", C.c_void_p),
                 ("chiN", C.c_double), ("kappaN", C.c_double), ("Re", C.c_double),
-                ("box", C.c_double * 3), ("grid", C.c_int32 * 3), ("move_halfwidth", C.c_double)]
+                ("box", C.c_double * 3), ("grid", C.c_int32 * 3), ("move_halfwidth", C.c_double),
+                ("smc_A", C.c_double)]
 
 
 class soma_options(C.Structure):
@@ -131,6 +132,7 @@ def _desc_array(systems: Sequence[SystemDesc]):
         d.box = (C.c_double * 3)(*s.box)
         d.grid = (C.c_int32 * 3)(*s.grid)
         d.move_halfwidth = s.move_halfwidth
+        d.smc_A = float(getattr(s, "smc_A", 0.0))
     return arr, keep
 
 

@@ -17,6 +17,7 @@ stand-ins at 128 beads per Re^3 with a grid cell of Re/4:
                  f ~U[0.3,0.7], chiN ~U[10,40], kappaN=50
   batched_mixed  256 systems mixing A/B blends, AB diblocks and ABA triblocks,
                  N ~U{8..128}, beads ~U[1e4,1e6], chiN ~U[0,50], kappaN ~U[25,100]
+  plain_large_smc  plain_large with bond-force-biased (smart) moves, A = 4e-4 Re^2
 """
 from __future__ import annotations
 
@@ -30,7 +31,7 @@ TYPE_A = 0
 TYPE_B = 1
 
 WORKLOAD_NAMES = ("plain_small", "plain_large", "mixed_large",
-                  "batched_uneven", "batched_mixed")
+                  "batched_uneven", "batched_mixed", "plain_large_smc")
 BASE_SEED = 20260609
 
 
@@ -124,6 +125,15 @@ def mixed_large() -> List[SystemDesc]:
     return [diblock_system(262144, 64, 0.5, 30.0, 50.0, (64, 64, 32), (256, 256, 128), "mixed_large")]
 
 
+def plain_large_smc() -> List[SystemDesc]:
+    """plain_large with bond-force-biased moves, A = 4e-4 Re^2: the Gaussian
+    part of the displacement has the rms per axis of the uniform cube."""
+    s = plain_large()[0]
+    s.smc_A = 4.0e-4
+    s.label = "plain_large_smc"
+    return [s]
+
+
 def batched_uneven(n_systems: int = 64, seed: Optional[int] = None,
                    chain_range=(512, 16384)) -> List[SystemDesc]:
     rng = np.random.default_rng(BASE_SEED + 4 if seed is None else seed)
@@ -167,7 +177,8 @@ def batched_mixed(n_systems: int = 256, seed: Optional[int] = None,
 
 def workload(name: str, **kw) -> List[SystemDesc]:
     return {"plain_small": plain_small, "plain_large": plain_large, "mixed_large": mixed_large,
-            "batched_uneven": batched_uneven, "batched_mixed": batched_mixed}[name](**kw)
+            "batched_uneven": batched_uneven, "batched_mixed": batched_mixed,
+            "plain_large_smc": plain_large_smc}[name](**kw)
 
 
 # Options per workload: position representation and count width.
@@ -177,6 +188,7 @@ WORKLOAD_OPTIONS = {
     "mixed_large": dict(pos_repr="cell", count_width=32, sweeps=100, reorder_every=100),
     "batched_uneven": dict(pos_repr="f32", count_width=16, sweeps=500, reorder_every=100),
     "batched_mixed": dict(pos_repr="cell", count_width=16, sweeps=200, reorder_every=100),
+    "plain_large_smc": dict(pos_repr="f32", count_width=16, sweeps=200, reorder_every=100),
 }
 
 

@@ -59,3 +59,26 @@ def two_bead_cell_probabilities(omega, n, L, k):
         * Wx[idx[2][:, None], idx[2][None, :]]
     P = np.exp(-omega[0])[:, None] * np.exp(-omega[1])[None, :] * Wpair
     return P / P.sum(), idx
+
+
+def smart_acceptance_two_beads(A, edge, k=3.0, n=4_000_000, seed=0):
+    """E[accept] of one bond-force-biased move of an N = 2 ideal chain in
+    equilibrium, by numpy Monte Carlo over the bond b ~ N(0, 1/k) and the
+    proposal d = A F + sqrt(2A) xi with F = -k b (F at the trial position
+    -k (b + d)); displacements of 0.99 cell edges or more are rejected.
+    Returns the estimate and its standard error."""
+    import math
+
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    b = rng.normal(0.0, 1.0 / math.sqrt(k), size=(n, 3))
+    xi = rng.normal(size=(n, 3))
+    F = -k * b
+    d = A * F + math.sqrt(2 * A) * xi
+    inside = (np.abs(d) < 0.99 * edge).all(axis=1)
+    b2 = b + d
+    dE = 0.5 * k * ((b2 ** 2).sum(1) - (b ** 2).sum(1))
+    F2 = -k * b2
+    lnq = (((d - A * F) ** 2).sum(1) - ((d + A * F2) ** 2).sum(1)) / (4 * A)
+    p = np.where(inside, np.minimum(1.0, np.exp(np.minimum(-dE + lnq, 0.0))), 0.0)
+    return p.mean(), p.std() / math.sqrt(n)

@@ -24,7 +24,7 @@ from scipy import stats
 
 import oracle
 from paper_2606_09356_amd import workloads as W
-from tests.helpers.closed_forms import two_bead_cell_probabilities
+from tests.helpers.closed_forms import smart_acceptance_two_beads, two_bead_cell_probabilities
 
 
 def ideal(n_chains, N, box, grid, A):
@@ -66,22 +66,6 @@ def test_smart_sweeps_keep_ideal_statistics(orc, mode):
     b = np.diff(O.positions().reshape(3, n_chains, N), axis=2).ravel()
     assert b.var() == pytest.approx(1.0 / (3 * (N - 1)), rel=0.01)
     assert acc / (40 * s.n_beads) > 0.9          # smart moves of this size are nearly always accepted
-
-
-def smart_acceptance_two_beads(A, edge, k=3.0, n=4_000_000, seed=0):
-    """E[accept] for one move of an N = 2 ideal chain in equilibrium (numpy)."""
-    rng = np.random.default_rng(seed)
-    b = rng.normal(0.0, 1.0 / math.sqrt(k), size=(n, 3))      # bond r_moved - r_other
-    xi = rng.normal(size=(n, 3))
-    F = -k * b
-    d = A * F + math.sqrt(2 * A) * xi
-    inside = (np.abs(d) < 0.99 * edge).all(axis=1)
-    b2 = b + d
-    dE = 0.5 * k * ((b2 ** 2).sum(1) - (b ** 2).sum(1))
-    F2 = -k * b2
-    lnq = (((d - A * F) ** 2).sum(1) - ((d + A * F2) ** 2).sum(1)) / (4 * A)
-    p = np.where(inside, np.minimum(1.0, np.exp(np.minimum(-dE + lnq, 0.0))), 0.0)
-    return p.mean(), p.std() / math.sqrt(n)
 
 
 def test_smart_acceptance_matches_monte_carlo_estimate(orc):
