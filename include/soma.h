@@ -17,7 +17,10 @@
  *            omega_B = [kN(phiA+phiB-1) + (chiN/2)(phiA-phiB)] / N
  *   chi-AB   omega_A = [chiN phiB + kN(phiA+phiB-1)] / N, omega_B symmetric
  *   move     r' = r + d, d uniform in [-delta, delta)^3; accept iff
- *            u < exp(-dE) with u uniform in [0, 1)
+ *            u < exp(-dE) with u uniform in [0, 1); or, per system, the
+ *            bond-force-biased move of SOMA (Sec. 2): d = A F + sqrt(2A) xi,
+ *            accept iff u < exp(-dE) q(r'->r) / q(r->r') with
+ *            q(r->r') ~ exp(-|r'-r-A F(r)|^2 / (4A)) (see smc_A)
  *   RNG      Philox4x32-10, key = seed, counter = (bead, chain, sweep, system)
  *   NGP      cell = floor(x / edge) mod n (unwrapped x, periodic box);
  *            linear cell index (ix * ny + iy) * nz + iz
@@ -76,7 +79,8 @@ enum { SOMA_HAM_HELFAND = 0, SOMA_HAM_CHI_AB = 1 };
  * 1 = B): a diblock or triblock melt sets n_chains_a = n_chains, an A/B
  * homopolymer blend an all-A pattern_a and an all-B pattern_b.
  * Limits: 2 <= N <= 128; 1 <= grid[d] <= 32768 with grid[0] * grid[1] <= 2^24;
- * move_halfwidth below 0.99 cell edges box[d]/grid[d]. */
+ * move_halfwidth below 0.99 cell edges box[d]/grid[d]; smc_A zero, or
+ * positive with sqrt(2 smc_A) at most half a cell edge. */
 typedef struct {
     int32_t n_chains;
     int32_t N;                 /* beads per chain */
