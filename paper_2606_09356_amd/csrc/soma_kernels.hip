@@ -9,7 +9,7 @@
 //   * One wavefront owns a tile of whole chains: lane p of a chain holds the
 //     bead pair (2p, 2p+1), so a chain of N <= 128 beads fits one wave and
 //     the bond neighbours of a bead sit in the same lane or the adjacent
-//     lane (cross-lane exchange with ds_bpermute; no LDS, no barrier).
+//     lane (cross-lane exchange with ds_bpermute; no barrier).
 //   * Positions are SoA with chains stored at an even stride, so each lane
 //     reads and writes one 8-byte pair per coordinate: fully coalesced.
 //   * The even pass moves bead 2p of every lane, the odd pass bead 2p+1;
@@ -29,6 +29,9 @@
 //     overlaps the move work.
 //   * Philox4x32-10 is counter based: one 128-bit block per (bead, logical
 //     chain, sweep, system); no RNG state lives in memory.
+//   * Per system, the trial move is uniform in a cube or bond-force biased
+//     ("smart", SOMA's move): the biased move draws FP64 Box-Muller normals
+//     and needs the moved even beads before the odd proposals.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -504,11 +507,12 @@ __device__ __forceinline__ SysView make_view(const DevSys &S)
 __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
 // ---------------------------------------------------------------------------
-// The sweep kernel: even pass, odd pass, density scatter, clear of the
-// count buffer two sweeps ahead.  One launch per sweep for every system.
+// The sweep kernel: even pass, odd pass, density delta (and, in density
+// mode 1, the fold of the previous delta).  One launch per sweep for every
+// system.
 // ---------------------------------------------------------------------------
-// Issue the position loads of one wave tile (lane p of chain g holds beads
-// 2p and 2p+1); used to prefetch the next tile while the current one moves.
+// Load the positions of one wave tile (lane p of chain g holds beads 2p and
+// 2p+1).
 template <class Bead>
 __device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0, Bead &b1)
 {
