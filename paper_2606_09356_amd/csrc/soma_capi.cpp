@@ -154,6 +154,15 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
         if (cells >= (int64_t(1) << 31)) return bad("too many cells");
         if ((int64_t)d.grid[0] * d.grid[1] > (int64_t(1) << 24)) return bad("grid[0] * grid[1] must be <= 2^24");
     }
+    // count words and chains are indexed with 32-bit values across the batch
+    int64_t words = 0, chains = 0;
+    for (int32_t k = 0; k < n_sys; ++k) {
+        const int64_t M = (int64_t)sys[k].grid[0] * sys[k].grid[1] * sys[k].grid[2];
+        words += ((M + 63) & ~int64_t(63)) * (opt->count_width == SOMA_COUNT_U16 ? 1 : 2);
+        chains += sys[k].n_chains;
+    }
+    if (words >= (int64_t(1) << 31)) { msg = "the systems' count words exceed 2^31 in total"; return SOMA_EINVAL; }
+    if (chains >= (int64_t(1) << 31)) { msg = "the systems' chains exceed 2^31 in total"; return SOMA_EINVAL; }
     return SOMA_OK;
 }
 

@@ -94,3 +94,14 @@ def test_create_rejects_short_or_misaligned_workspace(lib):
 
 def test_autotune_rejects_null_context(lib):
     assert lib.soma_autotune(None, 5, None) == S.SOMA_EINVAL
+
+
+def test_batch_totals_are_bounded(lib):
+    """Count words and chains are indexed with 32-bit values across a batch."""
+    big = W.diblock_system(64, 32, 0.5, 10.0, 50.0, (1024.0, 1024.0, 512.0), (4096, 4096, 64), "big")
+    n = C.c_size_t(0)
+    arr, keep = S._desc_array([big] * 2)
+    # 2^30 cells each: one system fits, two exceed 2^31 count words
+    one, keep1 = S._desc_array([big])
+    assert lib.soma_workspace_size(one, 1, C.byref(_opts()), C.byref(n)) == 0
+    assert lib.soma_workspace_size(arr, 2, C.byref(_opts()), C.byref(n)) == S.SOMA_EINVAL
