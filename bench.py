@@ -245,10 +245,12 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": prof["traffic_bytes_per_launch"] if prof else None,
                      "bytes_per_sweep": info["bytes_per_sweep"],
-                     "kernel": ("k_sweep (moves with fields from base + previous delta, folds the previous "
-                                "delta), one launch per sweep" if info["density_mode"] == 1 else
-                                "k_sweep + k_fold (moves with fields from the counts, then the delta fold), "
-                                "two launches per sweep"),
+                     "kernel": {0: "k_sweep + k_fold (moves with fields from the counts, then the delta fold), "
+                                   "two launches per sweep",
+                                1: "k_sweep (moves with fields from base + previous delta, folds the previous "
+                                   "delta), one launch per sweep",
+                                2: "k_sweep + k_fold_faces (moves emitting face fluxes, then the flux-divergence "
+                                   "fold), two launches per sweep"}[info["density_mode"]],
                      "avg_sweep_us_hip_events": sec / args.steps * 1e6},
         "observables": {k: obs[k] for k in ("Re2", "Re2_err", "Rg2", "Ebond_per_chain", "Enb_per_chain",
                                            "accept_ratio")},

@@ -106,11 +106,16 @@ typedef struct {
     int32_t pos_repr;          /* SOMA_POS_* */
     int32_t count_width;       /* SOMA_COUNT_* */
     int32_t use_graph;         /* nonzero: soma_mc_sweep replays a captured hipGraph per sweep count */
-    int32_t density_mode;      /* where the density delta is folded into the counts (accepted
-                                  cell changes always go to a per-sweep delta by atomics):
-                                  0: a streaming kernel after each sweep;
-                                  1: inside the next sweep's kernel, whose gathers then read
-                                  base + previous delta (two base, three delta buffers) */
+    int32_t density_mode;      /* how accepted cell changes reach the counts (always through
+                                  a per-sweep delta, merged per wave, by device atomics):
+                                  0: -1/+1 on the old and new cell's words, folded into the
+                                     counts by a streaming kernel after each sweep;
+                                  1: the same words, folded inside the next sweep's kernel,
+                                     whose gathers then read base + previous delta (two base,
+                                     three delta buffers);
+                                  2: face fluxes (one word per crossed cell face, so a
+                                     one-axis move costs one atomic instead of two), folded
+                                     by a kernel that adds each cell's flux divergence */
     int32_t reorder_every;     /* >0: spatially sort chains every this many sweeps; 0: never */
     int32_t waves_per_block;   /* 1..16 waves per workgroup; 0: library default */
     int32_t waves_per_cu;      /* >0: sweep grid of this many waves per compute unit, each wave
@@ -217,7 +222,7 @@ int soma_get_info(soma_ctx *ctx, soma_info *out);
  * the SOMA optimisation (Sec. 2.2).  For every candidate shape -- waves per
  * workgroup in {1, 2, 4, 8, 16}; one tile per wave, or a resident grid of
  * 8 or 32 waves per compute unit walking tile ranges; XCD-aware block order
- * on or off; density mode 0 or 1 -- times `trial_sweeps` sweeps (1..1000)
+ * on or off; density mode 0, 1 or 2 -- times `trial_sweeps` sweeps (1..1000)
  * after one warm-up sweep, and keeps the fastest for every later sweep.  The trial
  * sweeps are undone: positions, counts, acceptance counters, the status
  * word and the sweep counter are restored, so the trajectory is exactly
@@ -227,7 +232,7 @@ typedef struct {
     int32_t waves_per_block;   /* chosen shape */
     int32_t waves_per_cu;      /* 0: one tile per wave */
     int32_t xcd_remap;
-    int32_t density_mode;      /* chosen fold placement */
+    int32_t density_mode;      /* chosen density update */
     int32_t n_candidates;
     double us_per_sweep;       /* trial time of the chosen shape */
     double us_per_sweep_before;/* trial time of the shape in use at the call */

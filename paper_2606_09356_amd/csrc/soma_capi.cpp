@@ -26,10 +26,11 @@ namespace {
 thread_local std::string g_create_error;
 
 struct Layout {
-    size_t systems, tiles, chain_id, chain_id2, P[3], C[3], Q[3], D[3], keys, hist, bsum, perm, base, delta,
+    size_t systems, tiles, chain_id, chain_id2, P[3], C[3], Q[3], D[3], keys, hist, bsum, perm, base, delta, flux, chunks,
         omega, accept, status, partials, obs_out, staging, total;   // base: counts, delta: density delta
     int64_t total_slots = 0, total_cells = 0, total_chains = 0, count_words = 0;
     int n_tiles = 0;
+    int n_chunks = 0;      // fold chunks of density mode 2
     int64_t max_obs_blocks = 0, max_cells = 0;
 };
 
@@ -59,6 +60,10 @@ struct soma_ctx {
     // before sweep s); `rot` says the buffers are in that layout.  Otherwise
     // (canonical) the counts are base[0] and every delta is zero.
     bool rot = false;
+    // density mode 2: after its sweeps the flux buffer of the last sweep's
+    // parity still holds fluxes; the other one is clear for sweep flux_sweep
+    bool flux_dirty = false;
+    uint64_t flux_sweep = 0;
     int any_smc = 0;       // some system moves with bond-force-biased moves
     uint64_t sweep = 0;
     uint64_t last_reorder = ~uint64_t(0);
@@ -78,6 +83,9 @@ struct soma_ctx {
     // Count buffers base[0..1] and delta buffers delta[0..2], count_words each.
     uint32_t *base(int k) const { return reinterpret_cast<uint32_t *>(ws + L.base) + k * L.count_words; }
     uint32_t *delta(int k) const { return reinterpret_cast<uint32_t *>(ws + L.delta) + k * L.count_words; }
+    // face-flux buffers of density mode 2: two buffers of three arrays
+    uint32_t *flux() const { return reinterpret_cast<uint32_t *>(ws + L.flux); }
+    soma::FoldChunk *chunks() const { return reinterpret_cast<soma::FoldChunk *>(ws + L.chunks); }
     // Counts in the canonical layout.
     uint32_t *counts() const { return base(0); }
     float2 *omega() const { return reinterpret_cast<float2 *>(ws + L.omega); }
@@ -120,7 +128,7 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
     if (opt->count_width != SOMA_COUNT_U16 && opt->count_width != SOMA_COUNT_U32) { msg = "bad count_width"; return SOMA_EINVAL; }
     if (opt->waves_per_block < 0 || opt->waves_per_block > 16) { msg = "waves_per_block must be 0..16"; return SOMA_EINVAL; }
     if (opt->waves_per_cu < 0 || opt->waves_per_cu > 64) { msg = "waves_per_cu must be 0..64"; return SOMA_EINVAL; }
-    if (opt->density_mode != 0 && opt->density_mode != 1) { msg = "density_mode must be 0 or 1"; return SOMA_EINVAL; }
+    if (opt->density_mode < 0 || opt->density_mode > 2) { msg = "density_mode must be 0, 1 or 2"; return SOMA_EINVAL; }
     if (opt->reorder_every < 0) { msg = "reorder_every must be >= 0"; return SOMA_EINVAL; }
     if (opt->launch_order != 0 && opt->launch_order != 1) { msg = "launch_order must be 0 or 1"; return SOMA_EINVAL; }
     if (opt->sys_id_base < 0 || (int64_t)opt->sys_id_base + n_sys >= (int64_t(1) << 31)) { msg = "sys_id_base + n_sys must stay below 2^31"; return SOMA_EINVAL; }
@@ -161,7 +169,8 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
         words += ((M + 63) & ~int64_t(63)) * (opt->count_width == SOMA_COUNT_U16 ? 1 : 2);
         chains += sys[k].n_chains;
     }
-    if (words >= (int64_t(1) << 31)) { msg = "the systems' count words exceed 2^31 in total"; return SOMA_EINVAL; }
+    // (the face-flux words of density mode 2, 3 per count word, carry 32-bit keys)
+    if (words >= (int64_t(1) << 30)) { msg = "the systems' count words exceed 2^30 in total"; return SOMA_EINVAL; }
     if (chains >= (int64_t(1) << 31)) { msg = "the systems' chains exceed 2^31 in total"; return SOMA_EINVAL; }
     return SOMA_OK;
 }
@@ -271,6 +280,16 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     L.perm = take(sizeof(uint32_t) * chains);
     L.base = take(sizeof(uint32_t) * 2 * L.count_words);
     L.delta = take(sizeof(uint32_t) * 3 * L.count_words);
+    L.flux = take(sizeof(uint32_t) * 6 * L.count_words);
+    {
+        int64_t nch = 0;
+        for (int32_t k = 0; k < n_sys; ++k) {
+            const int64_t M = (int64_t)sys[k].grid[0] * sys[k].grid[1] * sys[k].grid[2];
+            nch += (M + soma::kFoldChunk - 1) / soma::kFoldChunk;
+        }
+        L.n_chunks = (int)nch;
+        L.chunks = take(sizeof(soma::FoldChunk) * (size_t)nch);
+    }
     L.omega = take(sizeof(float) * 2 * cells);
     L.accept = take(sizeof(uint64_t) * soma::kAcceptSlots * soma::kAcceptStride * n_sys);
     L.status = take(64);
@@ -343,7 +362,8 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
     a.base = c->base(0);
     a.delta = c->delta(0);
     a.count_words = c->L.count_words;
-    a.fold_in = c->density_mode;
+    a.density_mode = c->density_mode;
+    a.flux = c->flux();
     a.smc = c->any_smc;
     a.omega = c->omega();
     a.sweep_ctr = c->sweep_ctr();
@@ -381,10 +401,19 @@ int enter_rotation(soma_ctx *c)
     return SOMA_OK;
 }
 
-// The layout the context's density mode sweeps in.
+// The layout the context's density mode sweeps in.  Mode 2 needs the flux
+// buffer of the next sweep's parity clear: it is, when the sweeps continue
+// from the last mode-2 batch; otherwise both buffers are cleared.
 int sweep_layout(soma_ctx *c)
 {
-    return c->density_mode == 1 ? enter_rotation(c) : canonicalize(c);
+    if (c->density_mode == 1) return enter_rotation(c);
+    int rc = canonicalize(c);
+    if (rc != SOMA_OK) return rc;
+    if (c->density_mode == 2 && c->flux_dirty && c->sweep != c->flux_sweep) {
+        HIPCHK(c, soma::launch_fill_u32(c->flux(), 6 * c->L.count_words, 0u, c->stream));
+        c->flux_dirty = false;
+    }
+    return SOMA_OK;
 }
 
 // Rebuild the density of one system (or all when sys < 0) in the canonical
@@ -475,6 +504,18 @@ int record_sweeps(soma_ctx *c, int32_t n, hipStream_t st)
         HIPCHK(c, soma::launch_sweep(c->repr, c->cw, a, st));
         if (c->density_mode == 0)
             HIPCHK(c, soma::launch_fold(c->cw, c->counts(), c->delta(0), c->counts(), c->L.count_words, c->status(), st));
+        if (c->density_mode == 2) {
+            soma::FoldFacesArgs f{};
+            f.systems = c->d_sys();
+            f.chunks = c->chunks();
+            f.counts = c->counts();
+            f.flux = c->flux();
+            f.count_words = c->L.count_words;
+            f.sweep_ctr = c->sweep_ctr();
+            f.rel = (uint32_t)r;
+            f.status = c->status();
+            HIPCHK(c, soma::launch_fold_faces(c->cw, f, c->L.n_chunks, st));
+        }
     }
     HIPCHK(c, soma::launch_advance(c->sweep_ctr(), (uint32_t)n, st));
     return SOMA_OK;
@@ -651,10 +692,20 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
         return bail(hip_fail(c, e, "upload systems"));
     if ((e = hipMemcpyAsync(c->d_tiles(), c->tiles.data(), sizeof(Tile) * c->tiles.size(), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
         return bail(hip_fail(c, e, "upload tiles"));
+    std::vector<soma::FoldChunk> chunks;
+    for (size_t k = 0; k < c->sys.size(); ++k)
+        for (int64_t f = 0; f < c->sys[k].dev.n_cells; f += soma::kFoldChunk)
+            chunks.push_back(soma::FoldChunk{(uint32_t)k, 0u, f});
+    if ((int)chunks.size() != c->L.n_chunks) return bail(fail(c, SOMA_EDEVICE, "fold chunk table size"));
+    if (!chunks.empty() &&
+        (e = hipMemcpyAsync(c->chunks(), chunks.data(), sizeof(soma::FoldChunk) * chunks.size(), hipMemcpyHostToDevice,
+                            c->stream)) != hipSuccess)
+        return bail(hip_fail(c, e, "upload fold chunks"));
     // clear counts, fields, accept counters, status and sweep counter
     if ((rc = [&] {
              HIPCHK(c, soma::launch_fill_u32(c->base(0), 2 * c->L.count_words, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(c->delta(0), 3 * c->L.count_words, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(c->flux(), 6 * c->L.count_words, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->omega()), 2 * c->L.total_cells, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->accept()),
                                              2 * (int64_t)soma::kAcceptSlots * soma::kAcceptStride * n_sys, 0u, c->stream));
@@ -724,6 +775,10 @@ int soma_mc_sweep(soma_ctx *c, int32_t n)
         }
         c->sweep += (uint64_t)seg;
         left -= seg;
+    }
+    if (n > 0 && c->density_mode == 2) {
+        c->flux_dirty = true;
+        c->flux_sweep = c->sweep;
     }
     return SOMA_OK;
 }
@@ -1044,6 +1099,10 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
             return rc;
         }
         c->sweep += (uint64_t)trial_sweeps;
+        if (c->density_mode == 2) {
+            c->flux_dirty = true;
+            c->flux_sweep = c->sweep;
+        }
         return SOMA_OK;
     };
     auto time_shape = [&](int wpb, int wpcu, int xcd, int dm, double &us) -> int {
@@ -1066,7 +1125,7 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
     rc = time_shape(best.waves_per_block, best.waves_per_cu, best.xcd_remap, best.density_mode,
                     best.us_per_sweep_before);
     best.us_per_sweep = best.us_per_sweep_before;
-    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32}, kXcd[] = {1, 0}, kDm[] = {0, 1};
+    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32}, kXcd[] = {1, 0}, kDm[] = {0, 1, 2};
     for (int dm : kDm)
         for (int wpb : kWpb)
             for (int wpcu : kWpcu)

@@ -358,19 +358,23 @@ __device__ __forceinline__ uint2 counts_of(const RawCount &r)
 // rate; updates of one chain often hit the same count word (a chain carries
 // a count along: one bead leaves a cell that another bead of the same chain
 // enters), so merging a wave's updates first removes about a fifth of them.
-// Open addressing over kAggSlots slots: key = word index + 1 (0 = empty).
-// A wave makes at most 4 updates per lane, 256 in all, so a slot is always
+// Open addressing over SLOTS slots: key = word index + 1 (0 = empty).  A
+// wave makes at most 4 updates per lane with cell words (256 in all) and at
+// most 6 with face fluxes (384), so with 256 or 512 slots a slot is always
 // found and the probe loop ends.
-constexpr int kAggSlots = 256;
+constexpr int kAggSlotsCells = 256;
+constexpr int kAggSlotsFaces = 512;
 
+template <int SLOTS>
 __device__ __forceinline__ uint32_t agg_hash(uint32_t key)
 {
-    return (__umul24(key, 0x9E3779u) >> 10) & (kAggSlots - 1);
+    return (__umul24(key, 0x9E3779u) >> 10) & (SLOTS - 1);
 }
 
+template <int SLOTS>
 __device__ __forceinline__ void agg_insert(uint32_t *keys, uint32_t *vals, uint32_t key, uint32_t v, bool on)
 {
-    uint32_t h = agg_hash(key);
+    uint32_t h = agg_hash<SLOTS>(key);
     bool pending = on;
     while (__ballot(pending) != 0) {
         if (pending) {
@@ -379,17 +383,18 @@ __device__ __forceinline__ void agg_insert(uint32_t *keys, uint32_t *vals, uint3
                 atomicAdd(vals + h, v);
                 pending = false;
             } else {
-                h = (h + 1u) & (kAggSlots - 1);
+                h = (h + 1u) & (SLOTS - 1);
             }
         }
     }
 }
 
-// Empty the wave's table (each lane clears kAggSlots / 64 keys and values).
+// Empty the wave's table (each lane clears SLOTS / 64 keys and values).
+template <int SLOTS>
 __device__ __forceinline__ void agg_clear(uint32_t *keys, uint32_t *vals)
 {
     const int lane = (int)(threadIdx.x & 63);
-    for (int k = lane; k < kAggSlots; k += 64) {
+    for (int k = lane; k < SLOTS; k += 64) {
         keys[k] = 0u;
         vals[k] = 0u;
     }
@@ -533,23 +538,70 @@ __device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0
 
 // One wave tile of the sweep: the even pass, the odd pass and the density
 // delta of up to G whole chains, from positions already loaded by tile_load.
-// End of a wave tile: the density delta of the beads that changed cell,
-// merged per wave in LDS, then one device atomic per distinct word with a
-// nonzero sum; the acceptance count and the cell-range status.
+// Face fluxes of one bead that moved from cell o to cell n (wrapped
+// coordinates, at most one step per axis): the move is taken axis by axis,
+// x, y, then z, and each step adds the bead to the flux through one face:
+// F_a(c) counts the beads that crossed from c to c + e_a, so a step -1 from
+// c subtracts one from F_a(c - e_a).  Flux word of face (a, c) for type t:
+// a W + word(c, t).
 template <int CW>
-__device__ __forceinline__ void tile_finish(const SweepArgs &a, int wave, uint32_t sys, int64_t cell_off,
-                                            uint32_t *dcur, uint32_t *agg_keys, uint32_t *agg_vals,
-                                            bool m0, int old0, int nc0, int t0, bool m1, int old1, int nc1,
-                                            int t1, bool acc0, bool acc1, bool bad)
+__device__ __forceinline__ void emit_faces(uint32_t *keys, uint32_t *vals, int64_t W, int64_t cell_off,
+                                           CellPos o, const CellPos &n, int t, bool on, const SysView &v)
 {
+    const uint32_t inc = count_inc<CW>(t);
+    // x
+    {
+        const int k = n.x == o.x ? 0 : (n.x == wrap_step(o.x + 1, v.n0) ? 1 : -1);
+        CellPos f = o;
+        if (k < 0) f.x = n.x;
+        agg_insert<kAggSlotsFaces>(keys, vals, (uint32_t)count_word<CW>(cell_off + lin(f, v), t) + 1u,
+                                   k > 0 ? inc : 0u - inc, on && k != 0);
+        o.x = n.x;
+    }
+    // y
+    {
+        const int k = n.y == o.y ? 0 : (n.y == wrap_step(o.y + 1, v.n1) ? 1 : -1);
+        CellPos f = o;
+        if (k < 0) f.y = n.y;
+        agg_insert<kAggSlotsFaces>(keys, vals, (uint32_t)(W + count_word<CW>(cell_off + lin(f, v), t)) + 1u,
+                                   k > 0 ? inc : 0u - inc, on && k != 0);
+        o.y = n.y;
+    }
+    // z
+    {
+        const int k = n.z == o.z ? 0 : (n.z == wrap_step(o.z + 1, v.n2) ? 1 : -1);
+        CellPos f = o;
+        if (k < 0) f.z = n.z;
+        agg_insert<kAggSlotsFaces>(keys, vals, (uint32_t)(2 * W + count_word<CW>(cell_off + lin(f, v), t)) + 1u,
+                                   k > 0 ? inc : 0u - inc, on && k != 0);
+    }
+}
+
+// End of a wave tile: the density delta of the beads that changed cell --
+// cell words (density modes 0, 1) or face fluxes (mode 2) -- merged per wave
+// in LDS, then one device atomic per distinct word with a nonzero sum; the
+// acceptance count and the cell-range status.
+template <int CW, int DM>
+__device__ __forceinline__ void tile_finish(const SweepArgs &a, int wave, uint32_t sys, int64_t cell_off,
+                                            const SysView &v, uint32_t *dcur, uint32_t *agg_keys,
+                                            uint32_t *agg_vals, bool m0, const CellPos &o0, const CellPos &n0,
+                                            int t0, bool m1, const CellPos &o1, const CellPos &n1, int t1,
+                                            bool acc0, bool acc1, bool bad)
+{
+    constexpr int SLOTS = DM == 2 ? kAggSlotsFaces : kAggSlotsCells;
     const int lane = (int)(threadIdx.x & 63);
-    const uint32_t i0 = count_inc<CW>(t0), i1 = count_inc<CW>(t1);
-    agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + old0, t0) + 1u, 0u - i0, m0);
-    agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + nc0, t0) + 1u, i0, m0);
-    agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + old1, t1) + 1u, 0u - i1, m1);
-    agg_insert(agg_keys, agg_vals, count_word<CW>(cell_off + nc1, t1) + 1u, i1, m1);
+    if constexpr (DM == 2) {
+        emit_faces<CW>(agg_keys, agg_vals, a.count_words, cell_off, o0, n0, t0, m0, v);
+        emit_faces<CW>(agg_keys, agg_vals, a.count_words, cell_off, o1, n1, t1, m1, v);
+    } else {
+        const uint32_t i0 = count_inc<CW>(t0), i1 = count_inc<CW>(t1);
+        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(o0, v), t0) + 1u, 0u - i0, m0);
+        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(n0, v), t0) + 1u, i0, m0);
+        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(o1, v), t1) + 1u, 0u - i1, m1);
+        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(n1, v), t1) + 1u, i1, m1);
+    }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (int k = lane; k < kAggSlots; k += 64) {
+    for (int k = lane; k < SLOTS; k += 64) {
         const uint32_t key = agg_keys[k], v = agg_vals[k];
         if (key != 0u && v != 0u)
             __hip_atomic_fetch_add(dcur + (key - 1u), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -565,7 +617,7 @@ __device__ __forceinline__ void tile_finish(const SweepArgs &a, int wave, uint32
     }
 }
 
-template <int R, int CW, bool FI, class Bead>
+template <int R, int CW, int DM, class Bead>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                            const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
                                            uint32_t *agg_vals, Bead b0, Bead b1)
@@ -612,8 +664,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     // cells are gathered together: one memory latency instead of two.
     const Bead n0 = propose(b0, d0, v);
     const Bead n1 = propose(b1, d1, v);
-    const int nc0 = lin(step(c0, b0, n0, v), v);
-    const int nc1 = lin(step(c1, b1, n1, v), v);
+    const CellPos s0 = step(c0, b0, n0, v), s1 = step(c1, b1, n1, v);
+    const int nc0 = lin(s0, v);
+    const int nc1 = lin(s1, v);
     const bool g0 = active && nc0 != old0, g1 = has1 && nc1 != old1;
     float dw0 = 0.0f, dw1 = 0.0f;
     if (frozen) {
@@ -625,12 +678,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     } else {
         RawCount rn0{0u, 0u, 0u, 0u}, ro0{0u, 0u, 0u, 0u}, rn1{0u, 0u, 0u, 0u}, ro1{0u, 0u, 0u, 0u};
         if (g0) {
-            rn0 = load_raw<CW, FI>(cin, dprev, cell_off + nc0);
-            ro0 = load_raw<CW, FI>(cin, dprev, cell_off + old0);
+            rn0 = load_raw<CW, DM == 1>(cin, dprev, cell_off + nc0);
+            ro0 = load_raw<CW, DM == 1>(cin, dprev, cell_off + old0);
         }
         if (g1) {
-            rn1 = load_raw<CW, FI>(cin, dprev, cell_off + nc1);
-            ro1 = load_raw<CW, FI>(cin, dprev, cell_off + old1);
+            rn1 = load_raw<CW, DM == 1>(cin, dprev, cell_off + nc1);
+            ro1 = load_raw<CW, DM == 1>(cin, dprev, cell_off + old1);
         }
         if (g0) dw0 = omega_of(fc, counts_of<CW>(rn0), t0) - omega_of(fc, counts_of<CW>(ro0), t0);
         if (g1) dw1 = omega_of(fc, counts_of<CW>(rn1), t1) - omega_of(fc, counts_of<CW>(ro1), t1);
@@ -663,8 +716,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
         if (acc1) b1 = n1;
     }
     if (active) store_pair(A, slot, b0, b1);
-    tile_finish<CW>(a, wave, T.sys, cell_off, dcur, agg_keys, agg_vals, acc0 && nc0 != old0, old0, nc0, t0,
-                    acc1 && nc1 != old1, old1, nc1, t1, acc0, acc1, active && bad);
+    tile_finish<CW, DM>(a, wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals, acc0 && nc0 != old0, c0, s0, t0,
+                        acc1 && nc1 != old1, c1, s1, t1, acc0, acc1, active && bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -747,7 +800,7 @@ __device__ __forceinline__ float smc_log_ratio(const DevSys &S, float3 de, doubl
 }
 
 // Field difference between a trial cell and the old cell of one bead.
-template <int CW, bool FI>
+template <int CW, int DM>
 __device__ __forceinline__ float field_step(const SweepArgs &a, bool frozen, const FieldCoef &fc,
                                             const uint32_t *cin, const uint32_t *dprev, int64_t cell_off,
                                             int nc, int old, int t, bool gather)
@@ -760,8 +813,8 @@ __device__ __forceinline__ float field_step(const SweepArgs &a, bool frozen, con
     } else {
         RawCount rn{0u, 0u, 0u, 0u}, ro{0u, 0u, 0u, 0u};
         if (gather) {
-            rn = load_raw<CW, FI>(cin, dprev, cell_off + nc);
-            ro = load_raw<CW, FI>(cin, dprev, cell_off + old);
+            rn = load_raw<CW, DM == 1>(cin, dprev, cell_off + nc);
+            ro = load_raw<CW, DM == 1>(cin, dprev, cell_off + old);
             dw = omega_of(fc, counts_of<CW>(rn), t) - omega_of(fc, counts_of<CW>(ro), t);
         }
     }
@@ -771,7 +824,7 @@ __device__ __forceinline__ float field_step(const SweepArgs &a, bool frozen, con
 // One wave tile with smart moves.  The odd bead's proposal depends on the
 // even pass (its bond force uses the moved even beads), so the two passes
 // gather their fields one after the other.
-template <int R, int CW, bool FI, class Bead>
+template <int R, int CW, int DM, class Bead>
 __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                                const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
                                                uint32_t *agg_vals, Bead b0, Bead b1)
@@ -807,6 +860,7 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
     // even pass: bead 2p, neighbours 2p-1 (previous lane's odd bead) and 2p+1
     bool acc0;
     int nc0;
+    CellPos s0;
     {
         double xi[3];
         float u;
@@ -816,8 +870,9 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
         double3 F;
         bool inside;
         const Bead n0 = smc_propose(b0, left, hl, b1, hr, S, v, xi, F, inside);
-        nc0 = lin(step(c0, b0, n0, v), v);
-        const float dw = field_step<CW, FI>(a, frozen, fc, cin, dprev, cell_off, nc0, old0, t0,
+        s0 = step(c0, b0, n0, v);
+        nc0 = lin(s0, v);
+        const float dw = field_step<CW, DM>(a, frozen, fc, cin, dprev, cell_off, nc0, old0, t0,
                                             active && inside && nc0 != old0);
         const float3 de = bond(n0, b0, v);
         const float dd = dot3(de, de);
@@ -831,6 +886,7 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
     // odd pass: bead 2p+1, neighbours 2p (this lane, moved) and 2p+2 (next lane)
     bool acc1;
     int nc1;
+    CellPos s1;
     {
         double xi[3];
         float u;
@@ -840,8 +896,9 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
         double3 F;
         bool inside;
         const Bead n1 = smc_propose(b1, b0, true, right, hr, S, v, xi, F, inside);
-        nc1 = lin(step(c1, b1, n1, v), v);
-        const float dw = field_step<CW, FI>(a, frozen, fc, cin, dprev, cell_off, nc1, old1, t1,
+        s1 = step(c1, b1, n1, v);
+        nc1 = lin(s1, v);
+        const float dw = field_step<CW, DM>(a, frozen, fc, cin, dprev, cell_off, nc1, old1, t1,
                                             has1 && inside && nc1 != old1);
         const float3 de = bond(n1, b1, v);
         const float dd = dot3(de, de);
@@ -852,8 +909,8 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
         if (acc1) b1 = n1;
     }
     if (active) store_pair(A, slot, b0, b1);
-    tile_finish<CW>(a, wave, T.sys, cell_off, dcur, agg_keys, agg_vals, acc0 && nc0 != old0, old0, nc0, t0,
-                    acc1 && nc1 != old1, old1, nc1, t1, acc0, acc1, active && bad);
+    tile_finish<CW, DM>(a, wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals, acc0 && nc0 != old0, c0, s0, t0,
+                        acc1 && nc1 != old1, c1, s1, t1, acc0, acc1, active && bad);
 }
 
 // The sweep kernel: one launch per sweep for every system.  Wave w of the
@@ -864,23 +921,26 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
 // one-tile case.  With FI every thread also folds count words of the
 // previous sweep: the first word's loads are issued before the move work
 // and its stores after it, so they overlap.
-template <int R, int CW, bool LOOP, bool FI, bool SMC>
+template <int R, int CW, bool LOOP, int DM, bool SMC>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
+    constexpr bool FI = DM == 1;
+    constexpr int SLOTS = DM == 2 ? kAggSlotsFaces : kAggSlotsCells;
     const uint64_t s = *a.sweep_ctr + a.rel;
     const int64_t W = a.count_words;
-    // FI: counts of sweep s are B[s-1] + D[s-1]; this sweep adds to D[s],
-    // writes B[s] and clears D[s+1] (last read by sweep s-1)
+    // mode 1: counts of sweep s are B[s-1] + D[s-1]; this sweep adds to D[s],
+    // writes B[s] and clears D[s+1] (last read by sweep s-1).  Mode 2: the
+    // face fluxes of sweep s go to flux buffer s mod 2 (three W-word arrays).
     const uint32_t *cin = FI ? a.base + ((s + 1) & 1) * W : a.base;
     const uint32_t *dprev = FI ? a.delta + ((s + 2) % 3) * W : nullptr;
-    uint32_t *dcur = FI ? a.delta + (s % 3) * W : a.delta;
+    uint32_t *dcur = FI ? a.delta + (s % 3) * W : (DM == 2 ? a.flux + (s & 1) * 3 * W : a.delta);
     const int wave = wave_tile(a.waves_per_block, a.xcd_remap);
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // this wave's aggregation table (2 kAggSlots words of dynamic LDS per wave)
+    // this wave's aggregation table (2 SLOTS words of dynamic LDS per wave)
     HIP_DYNAMIC_SHARED(uint32_t, agg_lds)
-    uint32_t *agg_keys = agg_lds + (threadIdx.x >> 6) * (2 * kAggSlots);
-    uint32_t *agg_vals = agg_keys + kAggSlots;
+    uint32_t *agg_keys = agg_lds + (threadIdx.x >> 6) * (2 * SLOTS);
+    uint32_t *agg_vals = agg_keys + SLOTS;
     uint32_t fb = 0u, fd = 0u;
     if constexpr (FI) {
         if (gtid < W) {
@@ -895,21 +955,21 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         for (int t = t_begin; t < t_end; ++t) {
             Bead b0, b1;
             tile_load(a, t, b0, b1);
-            agg_clear(agg_keys, agg_vals);
+            agg_clear<SLOTS>(agg_keys, agg_vals);
             if (SMC && a.systems[a.tiles[t].sys].smc)
-                sweep_tile_smc<R, CW, FI>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile_smc<R, CW, DM>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
             else
-                sweep_tile<R, CW, FI>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile<R, CW, DM>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
         }
     } else {
         if (wave < a.n_tiles) {
             Bead b0, b1;
             tile_load(a, wave, b0, b1);
-            agg_clear(agg_keys, agg_vals);
+            agg_clear<SLOTS>(agg_keys, agg_vals);
             if (SMC && a.systems[a.tiles[wave].sys].smc)
-                sweep_tile_smc<R, CW, FI>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile_smc<R, CW, DM>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
             else
-                sweep_tile<R, CW, FI>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile<R, CW, DM>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
         }
     }
     if constexpr (FI) {
@@ -931,6 +991,58 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         }
         if (ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
     }
+    if constexpr (DM == 2) {
+        // clear the flux buffer of sweep s + 1 (folded after sweep s - 1);
+        // its 3 W words are a multiple of 4 and 16-byte aligned
+        uint4 *fn = reinterpret_cast<uint4 *>(a.flux + ((s + 1) & 1) * 3 * W);
+        const int64_t n4 = 3 * W / 4, nthreads = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t i = gtid; i < n4; i += nthreads) fn[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+// Density mode 2: counts += divergence of the face fluxes of sweep s, per
+// cell c of one system: n(c) += sum_a F_a(c - e_a) - F_a(c) (modular uint32,
+// both species at once for packed counts), with the range check of the
+// other folds.  (The sweep kernel of sweep s + 1 clears these fluxes.)  One
+// block per chunk of kFoldChunk cells of one system.
+template <int CW>
+__global__ __launch_bounds__(256) void k_fold_faces(FoldFacesArgs a)
+{
+    const FoldChunk ch = a.chunks[blockIdx.x];
+    const DevSys &S = a.systems[ch.sys];
+    const uint64_t s = *a.sweep_ctr + a.rel;
+    const int64_t W = a.count_words;
+    const uint32_t *F = a.flux + (s & 1) * 3 * W;
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const int64_t M = S.n_cells;
+    const int64_t end = ch.first + kFoldChunk < M ? ch.first + kFoldChunk : M;
+    constexpr int WPC = CW == COUNT_U16 ? 1 : 2;
+    // cell -> (ix, iy, iz) by FP64 reciprocals with one correction step
+    // (exact: cells < 2^31), not by integer division
+    const double inz = 1.0 / (double)nz, iny = 1.0 / (double)ny;
+    bool ovf = false;
+    for (int64_t c = ch.first + threadIdx.x; c < end; c += blockDim.x) {
+        const int ci = (int)c;
+        int r = (int)((double)ci * inz);
+        int iz = ci - r * nz;
+        if (iz < 0) { iz += nz; --r; } else if (iz >= nz) { iz -= nz; ++r; }
+        int ix = (int)((double)r * iny);
+        int iy = r - ix * ny;
+        if (iy < 0) { iy += ny; --ix; } else if (iy >= ny) { iy -= ny; ++ix; }
+        const int64_t cxm = ((int64_t)(ix == 0 ? nx - 1 : ix - 1) * ny + iy) * nz + iz;
+        const int64_t cym = ((int64_t)ix * ny + (iy == 0 ? ny - 1 : iy - 1)) * nz + iz;
+        const int64_t czm = ((int64_t)ix * ny + iy) * nz + (iz == 0 ? nz - 1 : iz - 1);
+        for (int j = 0; j < WPC; ++j) {
+            const int64_t w = WPC * (S.cell_off + c) + j;
+            const int64_t wx = WPC * (S.cell_off + cxm) + j, wy = WPC * (S.cell_off + cym) + j,
+                          wz = WPC * (S.cell_off + czm) + j;
+            const uint32_t d = (F[wx] - F[w]) + (F[W + wy] - F[W + w]) + (F[2 * W + wz] - F[2 * W + w]);
+            uint32_t out;
+            ovf |= fold_word<CW>(a.counts[w], d, out);
+            a.counts[w] = out;
+        }
+    }
+    if (ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
 }
 
 // Fold a density delta into counts and clear it: out = in + delta (out may
@@ -1395,18 +1507,21 @@ __global__ __launch_bounds__(256) void k_obs_finalize(const double *partials, in
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+template <int R, int CW, int DM, bool SMC>
+static void launch_sweep_d(const SweepArgs &a, int blocks, hipStream_t st)
+{
+    const dim3 g(blocks), b(64 * a.waves_per_block);
+    const size_t lds = sizeof(uint32_t) * 2 * (DM == 2 ? kAggSlotsFaces : kAggSlotsCells) * a.waves_per_block;
+    if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC>), g, b, lds, st, a);
+}
+
 template <int R, int CW, bool SMC>
 static hipError_t launch_sweep_s(const SweepArgs &a, int blocks, hipStream_t st)
 {
-    const dim3 g(blocks), b(64 * a.waves_per_block);
-    const size_t lds = sizeof(uint32_t) * 2 * kAggSlots * a.waves_per_block;
-    if (a.fold_in) {
-        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, true, SMC>), g, b, lds, st, a);
-        else hipLaunchKernelGGL((k_sweep<R, CW, false, true, SMC>), g, b, lds, st, a);
-    } else {
-        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, false, SMC>), g, b, lds, st, a);
-        else hipLaunchKernelGGL((k_sweep<R, CW, false, false, SMC>), g, b, lds, st, a);
-    }
+    if (a.density_mode == 1) launch_sweep_d<R, CW, 1, SMC>(a, blocks, st);
+    else if (a.density_mode == 2) launch_sweep_d<R, CW, 2, SMC>(a, blocks, st);
+    else launch_sweep_d<R, CW, 0, SMC>(a, blocks, st);
     return hipGetLastError();
 }
 
@@ -1460,6 +1575,14 @@ hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off
     if (blocks == 0) return hipSuccess;
     if (cw == COUNT_U16) hipLaunchKernelGGL((k_unpack_counts<COUNT_U16>), dim3(blocks), dim3(256), 0, st, counts, cell_off, n_cells, out);
     else hipLaunchKernelGGL((k_unpack_counts<COUNT_U32>), dim3(blocks), dim3(256), 0, st, counts, cell_off, n_cells, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_faces(int cw, const FoldFacesArgs &a, int n_chunks, hipStream_t st)
+{
+    if (n_chunks <= 0) return hipSuccess;
+    if (cw == COUNT_U16) hipLaunchKernelGGL((k_fold_faces<COUNT_U16>), dim3(n_chunks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_fold_faces<COUNT_U32>), dim3(n_chunks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

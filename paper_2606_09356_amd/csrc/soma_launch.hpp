@@ -20,8 +20,10 @@ struct SweepArgs {
     uint32_t *base;                // two count buffers of count_words words each
     uint32_t *delta;               // three delta buffers of count_words words each
     int64_t count_words;           // uint32 words per buffer
-    int fold_in;                   // 0: counts in base[0], delta in delta[0], folded by k_fold;
-                                   // 1: rotation, the sweep kernel folds the previous delta
+    int density_mode;              // 0: counts in base[0], delta in delta[0], folded by k_fold;
+                                   // 1: rotation, the sweep kernel folds the previous delta;
+                                   // 2: face fluxes in flux buffer s mod 2, folded by k_fold_faces
+    uint32_t *flux;                // mode 2: two buffers of three count_words-word arrays
     int smc;                       // some system uses bond-force-biased moves
     const float2 *omega;           // frozen fields, per cell (A, B)
     const uint64_t *sweep_ctr;     // sweeps done before this graph / launch sequence
@@ -103,6 +105,25 @@ hipError_t launch_density(int repr, int cw, const DensityArgs &a, hipStream_t st
 hipError_t launch_fields(int cw, const FieldArgs &a, hipStream_t st);
 hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off, int64_t n_cells,
                                 uint32_t *out, hipStream_t st);
+// Density mode 2: the fold of one sweep's face fluxes, one block per chunk
+// of kFoldChunk cells of one system.
+constexpr int kFoldChunk = 2048;
+struct FoldChunk {
+    uint32_t sys;                  // index into the system table
+    uint32_t pad;
+    int64_t first;                 // first cell of the chunk within its system
+};
+struct FoldFacesArgs {
+    const DevSys *systems;
+    const FoldChunk *chunks;
+    uint32_t *counts;              // base[0]
+    uint32_t *flux;
+    int64_t count_words;
+    const uint64_t *sweep_ctr;
+    uint32_t rel;
+    uint32_t *status;
+};
+hipError_t launch_fold_faces(int cw, const FoldFacesArgs &a, int n_chunks, hipStream_t st);
 hipError_t launch_fold(int cw, const uint32_t *counts_in, uint32_t *delta, uint32_t *counts_out, int64_t n,
                        uint32_t *status, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);

@@ -74,7 +74,7 @@ def test_invalid_descriptors_are_rejected(lib, field, value):
 def test_invalid_options_are_rejected(lib):
     arr, keep = S._desc_array(W.plain_small())
     n = C.c_size_t(0)
-    for kw in [dict(pos_repr=3), dict(count_width=7), dict(waves_per_block=17), dict(density_mode=2),
+    for kw in [dict(pos_repr=3), dict(count_width=7), dict(waves_per_block=17), dict(density_mode=3),
                dict(density_mode=-1), dict(sys_id_base=-1), dict(launch_order=2), dict(waves_per_cu=65)]:
         assert lib.soma_workspace_size(arr, 1, C.byref(_opts(**kw)), C.byref(n)) == S.SOMA_EINVAL, kw
 
@@ -98,10 +98,10 @@ def test_autotune_rejects_null_context(lib):
 
 def test_batch_totals_are_bounded(lib):
     """Count words and chains are indexed with 32-bit values across a batch."""
-    big = W.diblock_system(64, 32, 0.5, 10.0, 50.0, (1024.0, 1024.0, 512.0), (4096, 4096, 64), "big")
+    big = W.diblock_system(64, 32, 0.5, 10.0, 50.0, (1024.0, 1024.0, 256.0), (4096, 4096, 32), "big")
     n = C.c_size_t(0)
     arr, keep = S._desc_array([big] * 2)
-    # 2^30 cells each: one system fits, two exceed 2^31 count words
+    # 2^29 cells each: one system fits, two reach the 2^30 count-word bound
     one, keep1 = S._desc_array([big])
     assert lib.soma_workspace_size(one, 1, C.byref(_opts()), C.byref(n)) == 0
     assert lib.soma_workspace_size(arr, 2, C.byref(_opts()), C.byref(n)) == S.SOMA_EINVAL

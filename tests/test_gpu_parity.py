@@ -129,11 +129,11 @@ def test_fields_match_oracle(name):
     g.close()
 
 
-@pytest.mark.parametrize("reorder", [0, 1])
+@pytest.mark.parametrize("reorder,dm", [(0, 0), (1, 0), (0, 2), (1, 1)])
 @pytest.mark.parametrize("name", list(small_cases()))
-def test_single_and_multi_sweep_parity(name, reorder):
+def test_single_and_multi_sweep_parity(name, reorder, dm):
     systems, r, cw = small_cases()[name]
-    g, orcs = make_pair(systems, r, cw, reorder_every=reorder)
+    g, orcs = make_pair(systems, r, cw, reorder_every=reorder, density_mode=dm)
     total, mism = 0, 0
     for sweep in range(3):
         g.sweep(1)
@@ -208,7 +208,8 @@ def test_graph_tiling_and_xcd_invariance():
                                               (False, 7, 0, 0, 0), (True, 4, 1, 0, 0), (True, 2, 8, 0, 0),
                                               (True, 4, 0, 1, 0), (False, 4, 0, 2, 0), (True, 4, 0, 3, 0),
                                               (True, 4, 0, 0, 1), (False, 1, 0, 2, 1), (True, 2, 8, 3, 1),
-                                              (True, 16, 32, 0, 1)]:
+                                              (True, 16, 32, 0, 1), (True, 4, 0, 0, 2), (False, 1, 0, 2, 2),
+                                              (True, 2, 8, 3, 2), (True, 16, 32, 0, 2)]:
         g = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, use_graph=use_graph, waves_per_block=wpb,
                  waves_per_cu=wpcu, reorder_every=reorder, density_mode=dm)
         g.sweep(2)
@@ -241,7 +242,7 @@ def test_autotune_keeps_the_trajectory(r):
     b.sweep(2)
     t = a.autotune(trial_sweeps=2)
     print(f"[autotune {r}] {t}", flush=True)
-    assert t["n_candidates"] == 60 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
+    assert t["n_candidates"] == 90 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
     i = a.info()
     assert (i["waves_per_block"], i["waves_per_cu"], i["xcd_remap"], i["density_mode"]) == \
         (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"], t["density_mode"])
@@ -270,13 +271,13 @@ def test_batched_equals_each_system_alone():
     g.close()
 
 
-@pytest.mark.parametrize("r,dm", [("f32", 0), ("cell", 0), ("f32", 1), ("cell", 1)])
+@pytest.mark.parametrize("r,dm", [("f32", 0), ("cell", 0), ("f32", 1), ("cell", 1), ("f32", 2), ("cell", 2)])
 def test_checkpoint_resume_bit_exact(r, dm):
-    """A checkpoint taken in one density mode resumes bit-exactly in the other."""
+    """A checkpoint taken in one density mode resumes bit-exactly in another."""
     systems = W.batched_mixed(n_systems=3, seed=48, bead_range=(2000, 8000))
     a = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=dm)
     a.sweep(6)
-    b = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=1 - dm)
+    b = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=(dm + 1) % 3)
     b.sweep(3)
     saved = [b.state(k) for k in range(len(systems))]
     b.close()
