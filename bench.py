@@ -220,7 +220,7 @@ def main():
     B = info["n_beads"]
     prof = profiled(args.workload)
     if prof and prof.get("density_mode") != info["density_mode"]:
-        prof = None         # profiled with the other fold placement
+        prof = None         # profiled in another density mode
     moves_per_s = B * args.steps / sec
     ms_per_step = sec * 1e3 / args.steps
     achieved = info["bytes_per_sweep"] / (sec / args.steps) / 1e9
