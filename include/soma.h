@@ -33,8 +33,8 @@
  *     the context's GPU.
  *   - Work is enqueued on the HIP stream given at creation.  Calls that
  *     return data to the host synchronise that stream.
- *   - Device-side failures (count overflow, non-finite field, cell index
- *     overflow) are latched in a status word and reported by the next
+ *   - Device-side failures (count overflow, cell index overflow, an
+ *     internal consistency check) are latched in a status word and reported by the next
  *     synchronising call; after that the context only accepts
  *     soma_destroy and returns SOMA_ESTATE otherwise.
  *   - One context per stream; calls on one context are not thread-safe.
@@ -57,7 +57,7 @@ typedef enum {
     SOMA_ENOMEM = -2,      /* workspace too small */
     SOMA_EDEVICE = -3,     /* HIP runtime error */
     SOMA_EOVERFLOW = -4,   /* a density count exceeded its width, or a cell index left int32 range */
-    SOMA_ENONFINITE = -5,  /* a field value is not finite */
+    SOMA_ENONFINITE = -5,  /* a field value passed in is not finite */
     SOMA_ESTATE = -6       /* the context latched an earlier error */
 } soma_status;
 
@@ -132,7 +132,8 @@ typedef struct {
     double Rg2, Rg2_err;       /* mean radius of gyration squared and its standard error */
     double Ebond_per_chain;    /* (k/2) sum |b|^2 per chain, kT */
     double Enb_per_chain;      /* H_nb/kT per chain from the current counts */
-    double accept_ratio;       /* accepted / attempted moves since creation */
+    double accept_ratio;       /* accepted / attempted moves of the sweeps run on this context
+                                  (a resumed checkpoint counts from the resume) */
     uint64_t n_moves, n_accepted;
     uint64_t sweep;            /* sweeps done since creation */
 } soma_obs;
@@ -167,23 +168,53 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
 /* Release the context (not the workspace).  Synchronises its stream. */
 int soma_destroy(soma_ctx *ctx);
 
-/* Enqueue n_sweeps >= 0 full sweeps (move, density, field) of every system.
- * Asynchronous on the context's stream. */
+/* Enqueue n_sweeps >= 0 full SCMF sweeps of every system.  Defined by the
+ * paper's SOMA paragraph (Sec. 2: chains move independently by Monte-Carlo
+ * under quasi-instantaneous fields frozen for the sweep) and by Sec. 2.2,
+ * which names the two kernels of a time step: trial moves with energy
+ * evaluation (mc_polymer_iteration) and the rebuild of the particle density
+ * fields (update_density_fields).  One sweep here is: every bead makes one
+ * trial move (even beads, then odd beads) against its bonds and the frozen
+ * field of its type in its cell; the NGP counts are brought to the new
+ * positions; the fields follow from the counts (formulas at the top).
+ * Asynchronous on the context's stream; no host memory is touched.
+ * Returns SOMA_EINVAL for n_sweeps < 0, SOMA_ESTATE after a latched error,
+ * SOMA_EDEVICE if a launch fails.  Count overflow and cell-range errors
+ * raised by the kernels are reported by the next synchronising call. */
 int soma_mc_sweep(soma_ctx *ctx, int32_t n_sweeps);
 
 /* Wait for the stream and report latched device errors. */
 int soma_sync(soma_ctx *ctx);
 
-/* Density counts of system `sys` after the last sweep, as uint32
- * [2][nx][ny][nz] (A then B).  dst is device memory if dst_on_device,
- * else host memory (then the call synchronises). */
+/* Density counts of system `sys` after the last sweep: the particle
+ * density fields that Sec. 2.2's update_density_fields kernel rebuilds each
+ * step, here as exact nearest-grid-point bead counts per cell and species.
+ * Layout uint32 [2][nx][ny][nz] (A then B), linear cell (ix*ny + iy)*nz + iz.
+ * dst (2*nx*ny*nz words, owned by the caller) is device memory of the
+ * context's GPU if dst_on_device, else host memory.  Synchronises the
+ * stream and reports latched device errors (SOMA_EOVERFLOW, ...).
+ * SOMA_EINVAL for a bad system index or a null dst. */
 int soma_density(soma_ctx *ctx, int32_t sys, uint32_t *dst, int32_t dst_on_device);
 
-/* Fields omega_A, omega_B of system `sys` in kT, as float [2][nx][ny][nz]:
- * the frozen fields the next sweep will use. */
+/* Fields omega_A, omega_B of system `sys` in kT: the quasi-instantaneous
+ * fields of the SCMF algorithm (Sec. 2, SOMA paragraph), through which the
+ * non-bonded interactions act and which stay frozen during the next sweep;
+ * computed from the current counts with chiN and kappaN (formulas at the
+ * top), or the frozen array after soma_set_fields.  Layout float
+ * [2][nx][ny][nz] (A then B); dst (caller-owned, 2*nx*ny*nz floats) is
+ * device memory if dst_on_device, else host memory.  Synchronises; errors
+ * as soma_density. */
 int soma_fields(soma_ctx *ctx, int32_t sys, float *dst, int32_t dst_on_device);
 
-/* FP64 observables of system `sys` (compensated sums).  Synchronises. */
+/* FP64 observables of system `sys`: the validation quantities that Sec. 2.2
+ * moved to the GPU (initialisation and validation went from 235 s to under
+ * 2 s).  Per chain from the unwrapped positions: Re^2, Rg^2 and the bond
+ * energy; H_nb per chain from the counts; the acceptance ratio of the moves
+ * since creation (or the last soma_set_sweep).  Chain sums are Neumaier-
+ * compensated FP64 block sums, the only FP64 arithmetic on the GPU; the
+ * standard errors are sqrt(Var/n) over the n chains of the snapshot.
+ * `out` is host memory owned by the caller.  Synchronises; SOMA_EINVAL for a
+ * bad index or null out, latched device errors as soma_density. */
 int soma_observables(soma_ctx *ctx, int32_t sys, soma_obs *out);
 
 /* Unwrapped FP64 positions of system `sys` as host double [3][n_chains*N]

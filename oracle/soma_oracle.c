@@ -32,7 +32,8 @@
  *                A F + sqrt(2A) xi with F the bond force and xi standard
  *                normal, accepted with the Metropolis-Hastings ratio of the
  *                Gaussian proposal densities
- *     density    nearest-grid-point, cell = floor(x / cell edge) mod n
+ *     density    nearest-grid-point, cell = floor(x / cell edge) mod n, the
+ *                quotient exact, with the cell edge box/grid rounded to FP32
  *     RNG        Philox4x32-10 keyed by (seed) with counter
  *                (bead, chain, sweep, system)
  *
@@ -190,6 +191,20 @@ static int64_t wrap_index(int64_t i, int64_t n)
     return r < 0 ? r + n : r;
 }
 
+/* Unwrapped NGP index along axis d: the largest integer k with k * e <= x,
+ * for the cell edge e = box/grid rounded to FP32 (the edge of the stored
+ * representation, shared by every mode).  The FP64 quotient can round to
+ * the wrong side of an integer, so k is checked with products k * e that
+ * are exact in FP64 (|k| < 2^29 and e has a 24-bit significand). */
+static int64_t ngp_index(const orc_system *s, int d, double x)
+{
+    double e = (double)(float)cell_edge(s, d);
+    double k = floor(x / e);
+    while (k * e > x) k -= 1.0;
+    while ((k + 1.0) * e <= x) k += 1.0;
+    return (int64_t)k;
+}
+
 static int64_t cell_of(const orc_system *s, const orc_state *st, int64_t b)
 {
     int64_t B = n_beads(s);
@@ -199,7 +214,7 @@ static int64_t cell_of(const orc_system *s, const orc_state *st, int64_t b)
         if (st->mode == 2)
             i = st->cell[d * B + b];
         else
-            i = (int64_t)floor(get_pos(s, st, d, b) / cell_edge(s, d));
+            i = ngp_index(s, d, get_pos(s, st, d, b));
         idx[d] = wrap_index(i, s->grid[d]);
     }
     return (idx[0] * s->grid[1] + idx[1]) * s->grid[2] + idx[2];
@@ -415,7 +430,7 @@ uint64_t orc_sweep(const orc_system *s, orc_state *st, uint64_t seed, uint32_t s
                     if (st->mode == 2)
                         ia = c_new[a];
                     else
-                        ia = (int64_t)floor(r_new[a] / cell_edge(s, a));
+                        ia = ngp_index(s, a, r_new[a]);
                     idx[a] = wrap_index(ia, s->grid[a]);
                 }
                 int64_t cell_new = (idx[0] * s->grid[1] + idx[1]) * s->grid[2] + idx[2];

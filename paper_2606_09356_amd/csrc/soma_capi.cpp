@@ -66,6 +66,9 @@ struct soma_ctx {
     uint64_t flux_sweep = 0;
     int any_smc = 0;       // some system moves with bond-force-biased moves
     uint64_t sweep = 0;
+    // sweeps run on this context (the acceptance counters count their moves);
+    // unlike `sweep` it is not moved by soma_set_sweep
+    uint64_t swept = 0;
     uint64_t last_reorder = ~uint64_t(0);
     int latched = SOMA_OK;
     std::string err;
@@ -207,11 +210,14 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
             v.n_chains_a = d.n_chains_a;
             v.sys_id = (uint32_t)(opt->sys_id_base + k);
             v.frozen = 0;
+            v.edge_dyadic = 1;
             for (int a = 0; a < 3; ++a) {
                 v.n[a] = d.grid[a];
                 v.inv_n[a] = (float)(1.0 / d.grid[a]);
                 v.edge[a] = (float)(d.box[a] / d.grid[a]);
                 v.inv_edge[a] = (float)(1.0 / (double)v.edge[a]);
+                int ex = 0;
+                if (std::frexp((double)v.edge[a], &ex) != 0.5) v.edge_dyadic = 0;
             }
             const double k_spring = 3.0 * (d.N - 1) / (d.Re * d.Re);
             v.k_half = (float)(0.5 * k_spring);
@@ -321,7 +327,6 @@ int sync_status(soma_ctx *c)
     HIPCHK(c, hipMemcpy(&st, c->status(), sizeof st, hipMemcpyDeviceToHost));
     if (st & soma::ST_COUNT_OVERFLOW) { c->latched = SOMA_EOVERFLOW; return fail(c, SOMA_EOVERFLOW, "density count exceeded its width"); }
     if (st & soma::ST_CELL_OVERFLOW) { c->latched = SOMA_EOVERFLOW; return fail(c, SOMA_EOVERFLOW, "bead cell index left the int32 range (or a coordinate is not finite)"); }
-    if (st & soma::ST_NONFINITE) { c->latched = SOMA_ENONFINITE; return fail(c, SOMA_ENONFINITE, "non-finite field value"); }
     if (st & soma::ST_INTERNAL) { c->latched = SOMA_EDEVICE; return fail(c, SOMA_EDEVICE, "internal consistency check failed in the chain reorder"); }
     return SOMA_OK;
 }
@@ -774,6 +779,7 @@ int soma_mc_sweep(soma_ctx *c, int32_t n)
             if ((rc = record_sweeps(c, seg, c->stream)) != SOMA_OK) return rc;
         }
         c->sweep += (uint64_t)seg;
+        c->swept += (uint64_t)seg;
         left -= seg;
     }
     if (n > 0 && c->density_mode == 2) {
@@ -873,7 +879,7 @@ int soma_observables(soma_ctx *c, int32_t sys, soma_obs *out)
     out->Ebond_per_chain = q[4] / n;
     out->Enb_per_chain = (B / (double)h.dev.n_cells) / h.d.N * q[5] / n;
     out->sweep = c->sweep;
-    out->n_moves = (uint64_t)(c->sweep * (uint64_t)B);
+    out->n_moves = (uint64_t)(c->swept * (uint64_t)B);
     out->n_accepted = acc;
     out->accept_ratio = out->n_moves ? (double)acc / (double)out->n_moves : 0.0;
     return SOMA_OK;

@@ -109,7 +109,22 @@ struct SysView {            // the per-system scalars a wave needs (SGPR residen
     float inv_n0, inv_n1, inv_n2;
     float e0, e1, e2;
     float ie0, ie1, ie2;
+    bool dyadic;            // every edge a power of two: x * (1/edge) is the exact quotient
 };
+
+// floor(x / e) of the exact quotient for the FP32 cell edge e.  The product
+// with the rounded reciprocal can be one off next to a face when e is not a
+// power of two; the sign of x - k e, exact after one FMA rounding, corrects
+// it (|x / e| < 2^22, so the product is within one of the quotient).
+__device__ __forceinline__ float floor_div(float x, float e, float ie, bool dyadic)
+{
+    float k = floorf(x * ie);
+    if (!dyadic) {
+        if (fmaf(-k, e, x) < 0.0f) k -= 1.0f;
+        else if (fmaf(-(k + 1.0f), e, x) >= 0.0f) k += 1.0f;
+    }
+    return k;
+}
 
 struct BeadF32 {
     float x, y, z;
@@ -168,9 +183,9 @@ struct CellPos {
 __device__ __forceinline__ CellPos locate(const BeadF32 &a, const SysView &v, bool &bad)
 {
     CellPos c;
-    c.fx = floorf(a.x * v.ie0);
-    c.fy = floorf(a.y * v.ie1);
-    c.fz = floorf(a.z * v.ie2);
+    c.fx = floor_div(a.x, v.e0, v.ie0, v.dyadic);
+    c.fy = floor_div(a.y, v.e1, v.ie1, v.dyadic);
+    c.fz = floor_div(a.z, v.e2, v.ie2, v.dyadic);
     const float lim = (float)kCellLimit;
     if (!(fabsf(c.fx) < lim && fabsf(c.fy) < lim && fabsf(c.fz) < lim)) {
         bad = true;
@@ -205,9 +220,9 @@ __device__ __forceinline__ int clamp1(int k) { return k < -1 ? -1 : (k > 1 ? 1 :
 __device__ __forceinline__ CellPos step(const CellPos &o, const BeadF32 &, const BeadF32 &n, const SysView &v)
 {
     CellPos c;
-    c.fx = floorf(n.x * v.ie0);
-    c.fy = floorf(n.y * v.ie1);
-    c.fz = floorf(n.z * v.ie2);
+    c.fx = floor_div(n.x, v.e0, v.ie0, v.dyadic);
+    c.fy = floor_div(n.y, v.e1, v.ie1, v.dyadic);
+    c.fz = floor_div(n.z, v.e2, v.ie2, v.dyadic);
     c.x = wrap_step(o.x + clamp1((int)(c.fx - o.fx)), v.n0);
     c.y = wrap_step(o.y + clamp1((int)(c.fy - o.fy)), v.n1);
     c.z = wrap_step(o.z + clamp1((int)(c.fz - o.fz)), v.n2);
@@ -506,6 +521,7 @@ __device__ __forceinline__ SysView make_view(const DevSys &S)
     v.inv_n0 = S.inv_n[0]; v.inv_n1 = S.inv_n[1]; v.inv_n2 = S.inv_n[2];
     v.e0 = S.edge[0]; v.e1 = S.edge[1]; v.e2 = S.edge[2];
     v.ie0 = S.inv_edge[0]; v.ie1 = S.inv_edge[1]; v.ie2 = S.inv_edge[2];
+    v.dyadic = S.edge_dyadic != 0;
     return v;
 }
 

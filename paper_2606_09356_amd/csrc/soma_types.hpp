@@ -19,9 +19,11 @@ constexpr int kAcceptStride = 8;          // uint64 words between slots (64 B)
 enum Repr : int { REPR_F32 = 0, REPR_CELL = 1 };
 enum CountW : int { COUNT_U16 = 0, COUNT_U32 = 1 };
 
+// Device status bits, latched by the kernels and read at synchronising calls.
+// (Fields are never non-finite on the device: they are affine in integer
+// counts, and a frozen field array is checked on the host when it is set.)
 enum StatusBits : uint32_t {
     ST_COUNT_OVERFLOW = 1u,
-    ST_NONFINITE = 2u,
     ST_CELL_OVERFLOW = 4u,
     ST_INTERNAL = 8u,
 };
@@ -40,6 +42,7 @@ struct alignas(16) DevSys {
     uint32_t sys_id;       // Philox counter word 3
     int32_t n[3];          // grid
     int32_t frozen;        // 1: fields come from the frozen array, else from the counts
+    int32_t edge_dyadic;   // 1: every cell edge is a power of two (x * (1/edge) is exact)
     float inv_n[3];        // 1 / n, for the periodic wrap
     float edge[3];         // cell edge (FP32)
     float inv_edge[3];     // 1 / edge (FP32)

@@ -82,3 +82,27 @@ def smart_acceptance_two_beads(A, edge, k=3.0, n=4_000_000, seed=0):
     lnq = (((d - A * F) ** 2).sum(1) - ((d + A * F2) ** 2).sum(1)) / (4 * A)
     p = np.where(inside, np.minimum(1.0, np.exp(np.minimum(-dE + lnq, 0.0))), 0.0)
     return p.mean(), p.std() / math.sqrt(n)
+
+
+def ideal_chain_re2_variance(Re=1.0):
+    """Per-chain variance of Re^2 = |r_{N-1} - r_0|^2 for an ideal chain: the
+    end-to-end vector has three independent N(0, Re^2/3) components, so
+    3 Re^2/Re^2 is chi-squared with 3 degrees of freedom and
+    Var(Re^2) = (Re^2/3)^2 * 2 * 3 = (2/3) Re^4."""
+    return 2.0 / 3.0 * Re ** 4
+
+
+def ideal_chain_rg2_moments(N, Re=1.0):
+    """Exact mean and per-chain variance of Rg^2 = (1/N) sum_i |r_i - r_cm|^2
+    for a discrete Gaussian chain of N beads with bond components
+    N(0, s2), s2 = Re^2 / (3 (N - 1)).
+
+    Per axis, Rg^2 is the quadratic form b^T Q b of the N-1 bond components
+    b, with Q = L^T C L / N (L: bead i = sum of the bonds before it; C: the
+    centring projector).  For b ~ N(0, s2 I): mean s2 tr Q, variance
+    2 s2^2 tr Q^2; the three axes are independent."""
+    s2 = Re ** 2 / (3.0 * (N - 1))
+    L = np.tril(np.ones((N, N - 1)), -1)
+    C = np.eye(N) - np.full((N, N), 1.0 / N)
+    Q = L.T @ C @ L / N
+    return 3.0 * s2 * np.trace(Q), 3.0 * 2.0 * s2 ** 2 * np.trace(Q @ Q)

@@ -289,6 +289,11 @@ def test_checkpoint_resume_bit_exact(r, dm):
             c.set_state(k, st[0], st[1])
     c.set_sweep(3)
     c.sweep(3)
+    for k, sysd in enumerate(systems):
+        # acceptance counts the three sweeps run on the resumed context
+        oc = c.observables(k)
+        assert oc["n_moves"] == 3 * sysd.n_beads and oc["sweep"] == 6
+        assert 0.3 < oc["accept_ratio"] < 1.0
     for k in range(len(systems)):
         sa, sc = a.state(k), c.state(k)
         if r == "f32":
@@ -397,4 +402,39 @@ def test_full_size_single_sweep_parity(name):
         o.fields()
     print(f"[full-size] {name}: {mism} differing beads of {total} decisions", flush=True)
     assert mism / total <= 1e-6, (mism, total)
+    g.close()
+
+
+def face_system():
+    # cell edge 1.275 / 25 = 0.051: not a power of two, so the GPU's product
+    # with the FP32 reciprocal needs its correction next to every face
+    return W.diblock_system(2048, 8, 0.5, 20.0, 50.0, (1.275, 1.275, 1.275), (25, 25, 25), "faces")
+
+
+def face_positions(s, seed=5):
+    from tests.helpers.positions import face_adjacent_fp32
+    edge32 = np.float32(s.box[0] / s.grid[0])
+    rng = np.random.default_rng(seed)
+    xs = face_adjacent_fp32(edge32, list(range(-30, 60, 3)), rng)
+    xyz = W.gaussian_walks(s, seed=seed)
+    # bead 0 of each chain on a face-adjacent coordinate in every axis; the
+    # walk around it shifted with it
+    shift = np.stack([rng.choice(xs, size=s.n_chains) for _ in range(3)]) - xyz[:, 0::s.N]
+    return xyz + np.repeat(shift, s.N, axis=1)
+
+
+@pytest.mark.parametrize("r,cw", [("f32", 16), ("cell", 32)])
+def test_non_dyadic_edge_faces_density_and_sweep(r, cw):
+    s = face_system()
+    xyz = face_positions(s)
+    g = Soma([s], seed=SEED, pos_repr=r, count_width=cw)
+    g.set_positions(0, xyz)
+    o = oracle.OracleSystem(s, mode=oracle.MODE_F32 if r == "f32" else oracle.MODE_CELL)
+    o.set_positions(xyz)
+    assert (g.density(0) == o.counts).all()
+    g.sweep(1)
+    o.sweep(SEED, 0)
+    o.density()
+    assert same_state(g, 0, o).all()
+    assert (g.density(0) == o.counts).all()
     g.close()

@@ -20,6 +20,7 @@ import numpy as np
 import pytest
 
 from paper_2606_09356_amd import workloads as W
+from tests.helpers.positions import face_adjacent_fp32
 
 
 def small_system(n_chains=4, N=4, grid=(4, 5, 6), box=(1.0, 1.25, 1.5), chiN=20.0, kappaN=50.0,
@@ -165,3 +166,30 @@ def test_cell_offset_representation_round_trip(orc):
     assert (O.cell == np.floor(xyz / 0.25)).mean() > 0.999
     back = O.positions()
     assert np.abs(back - xyz).max() < 2 ** -26    # FP32 offset resolution below 0.25
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ngp_cell_is_exact_quotient_for_non_dyadic_edge(orc, mode):
+    """NGP cell = floor(x / e) of the exact quotient, e = box/grid rounded to
+    FP32, checked with rational arithmetic on coordinates within a few ulps of
+    the faces of a grid whose edge (1.275 / 25 = 0.051) is not a power of two."""
+    from fractions import Fraction
+    box, grid = 1.275, 25
+    edge32 = np.float32(box / grid)
+    rng = np.random.default_rng(11)
+    xs = face_adjacent_fp32(edge32, list(range(-30, 60, 7)), rng)
+    n = len(xs)
+    s = W.diblock_system(n, 2, 0.5, 0.0, 0.0, (box, box, box), (grid, grid, grid))
+    O = orc.OracleSystem(s, mode=mode)
+    xyz = np.zeros((3, 2 * n))
+    xyz[0, 0::2] = xs                       # bead 0 (type A) of every chain on the test coordinate
+    xyz[0, 1::2] = 0.5 * float(edge32)      # bead 1 (type B) in the middle of x-cell 0
+    xyz[1:, :] = 0.5 * float(edge32)
+    O.set_positions(xyz)
+    E = Fraction(float(edge32))
+    expect = np.zeros(s.n_cells, np.uint32)
+    for x in xs:
+        k = math.floor(Fraction(x) / E)
+        expect[(k % grid) * grid * grid] += 1
+    assert (O.counts[0] == expect).all()
+    assert O.counts[1][0] == n and O.counts[1].sum() == n
