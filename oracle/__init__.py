@@ -6,7 +6,8 @@ never imports it.  It shares no code with the GPU library: the only common
 inputs are the seeded workloads in ``paper_2606_09356_amd.workloads``.
 
 Modes: 0 = FP64 positions, 1 = FP32-stored positions, 2 = int32 cell + FP32
-offset stored positions (energies always FP64).
+offset stored positions (energies always FP64).  Coupling extensions: target
+fields with placement and an umbrella potential, walls and conversion zones.
 """
 from __future__ import annotations
 
@@ -38,12 +39,15 @@ class _System(C.Structure):
                 ("ham_form", C.c_int32), ("pattern_a", C.c_void_p), ("pattern_b", C.c_void_p),
                 ("chiN", C.c_double), ("kappaN", C.c_double), ("Re", C.c_double),
                 ("box", C.c_double * 3), ("grid", C.c_int32 * 3),
-                ("move_halfwidth", C.c_double), ("sys_id", C.c_uint32), ("smc_A", C.c_double)]
+                ("move_halfwidth", C.c_double), ("sys_id", C.c_uint32), ("smc_A", C.c_double),
+                ("umb_lambda", C.c_double), ("umb_target", C.c_void_p),
+                ("wall", C.c_int32 * 2), ("zone", C.c_int32 * 2)]
 
 
 class _State(C.Structure):
     _fields_ = [("mode", C.c_int32), ("x", C.c_void_p), ("xf", C.c_void_p),
-                ("cell", C.c_void_p), ("off", C.c_void_p)]
+                ("cell", C.c_void_p), ("off", C.c_void_p), ("chain_class", C.c_void_p),
+                ("conv", C.c_uint64 * 2)]
 
 
 class _Obs(C.Structure):
@@ -73,6 +77,11 @@ def lib():
         L.orc_run.argtypes = [P, P, C.c_uint64, C.c_uint32, C.c_int32, P, P, C.c_int32]
         L.orc_run.restype = C.c_uint64
         L.orc_init_walks.argtypes = [P, C.c_uint64, P]
+        L.orc_init_walks.restype = C.c_int
+        L.orc_place_from_fields.argtypes = [P, P, C.c_uint64, P, P, P]
+        L.orc_place_from_fields.restype = C.c_int
+        L.orc_convert.argtypes = [P, P]
+        L.orc_convert.restype = None
         L.orc_observables.argtypes = [P, P, P, P, P]
         L.orc_neumaier_sum.argtypes = [P, C.c_int64]
         L.orc_neumaier_sum.restype = C.c_double
@@ -111,6 +120,9 @@ class OracleSystem:
     """One system of the oracle: its description, stored positions, counts and fields."""
 
     def __init__(self, desc, sys_id: int = 0, mode: int = MODE_F64):
+        """Walls and conversion zones come from the descriptor's optional
+        ``walls`` ((lo, hi) z-cell faces) and ``zones`` ((lower, upper) widths
+        in z cells) attributes."""
         self.desc = desc
         self.mode = mode
         self._pa = np.ascontiguousarray(desc.pattern_a, dtype=np.uint8)
@@ -125,15 +137,24 @@ class OracleSystem:
         s.move_halfwidth = desc.move_halfwidth
         s.smc_A = float(getattr(desc, "smc_A", 0.0))
         s.sys_id = sys_id
+        walls = getattr(desc, "walls", None) or (0, 0)
+        zones = getattr(desc, "zones", None) or (0, 0)
+        s.wall = (C.c_int32 * 2)(*walls)
+        s.zone = (C.c_int32 * 2)(*zones)
+        s.umb_lambda = 0.0
+        s.umb_target = None
+        self._target = None
         self._sys = s
         B, M = desc.n_beads, desc.n_cells
         self.x = np.zeros((3, B), np.float64) if mode == MODE_F64 else None
         self.xf = np.zeros((3, B), np.float32) if mode == MODE_F32 else None
         self.cell = np.zeros((3, B), np.int32) if mode == MODE_CELL else None
         self.off = np.zeros((3, B), np.float32) if mode == MODE_CELL else None
+        self.chain_class = (np.arange(desc.n_chains) >= desc.n_chains_a).astype(np.uint8)
         st = _State()
         st.mode = mode
         st.x, st.xf, st.cell, st.off = _ptr(self.x), _ptr(self.xf), _ptr(self.cell), _ptr(self.off)
+        st.chain_class = _ptr(self.chain_class)
         self._st = st
         self.counts = np.zeros((2, M), np.uint32)
         self.omega = np.zeros((2, M), np.float64)
@@ -162,8 +183,40 @@ class OracleSystem:
 
     def init_walks(self, seed: int) -> np.ndarray:
         out = np.zeros((3, self.desc.n_beads), np.float64)
-        lib().orc_init_walks(self.sp, seed, _ptr(out))
+        rc = lib().orc_init_walks(self.sp, seed, _ptr(out))
+        if rc != 0:
+            raise ValueError(f"initial walks failed ({rc}): chains do not fit between the walls")
         return out
+
+    # -- coupling: target fields, umbrella, conversion zones ----------------
+    def set_target(self, phi_target: np.ndarray):
+        """Target concentration fields [2][M] (phi_A, phi_B) for placement and umbrella."""
+        self._target = np.ascontiguousarray(np.asarray(phi_target, dtype=np.float64).reshape(2, -1))
+        self._sys.umb_target = _ptr(self._target)
+
+    def set_umbrella(self, lam: float):
+        """Umbrella strength lambda (0 switches it off); needs set_target."""
+        if lam > 0 and self._target is None:
+            raise ValueError("set_target first")
+        self._sys.umb_lambda = float(lam)
+
+    def place_from_fields(self, seed: int):
+        """Positions of the placement from the target fields; returns (xyz, targets, cells)."""
+        B, n = self.desc.n_beads, self.desc.n_chains
+        xyz = np.zeros((3, B), np.float64)
+        tg = np.zeros((3, n), np.float64)
+        cells = np.zeros(n, np.int64)
+        rc = lib().orc_place_from_fields(self.sp, self.stp, seed, _ptr(xyz), _ptr(tg), _ptr(cells))
+        if rc != 0:
+            raise ValueError(f"placement failed ({rc})")
+        return xyz, tg, cells
+
+    def convert(self):
+        lib().orc_convert(self.sp, self.stp)
+
+    @property
+    def conversions(self):
+        return int(self._st.conv[0]), int(self._st.conv[1])
 
     # -- steps --------------------------------------------------------------
     def density(self) -> np.ndarray:

@@ -100,6 +100,10 @@ typedef struct {
     double move_halfwidth;
     uint32_t sys_id;
     double smc_A;             /* > 0: smart moves with this A (Re^2); 0: uniform moves */
+    double umb_lambda;        /* umbrella strength lambda (kT); 0: no umbrella */
+    const double *umb_target; /* [2][M] target phi_A, phi_B (umbrella and placement) */
+    int32_t wall[2];          /* walls at the z-cell faces wall[0] < wall[1]; wall[1] == 0: none */
+    int32_t zone[2];          /* z-cell widths of the conversion zones at the lower, upper wall */
 } orc_system;
 
 typedef struct {
@@ -108,15 +112,27 @@ typedef struct {
     float *xf;       /* mode 1: [3][B] */
     int32_t *cell;   /* mode 2: [3][B] */
     float *off;      /* mode 2: [3][B] */
+    uint8_t *chain_class; /* [n_chains]: 0 = pattern_a, 1 = pattern_b; NULL: by n_chains_a */
+    uint64_t conv[2];     /* chains converted to class a (lower zone) and to class b (upper zone) */
 } orc_state;
 
 static int64_t n_beads(const orc_system *s) { return (int64_t)s->n_chains * s->N; }
 static int64_t n_cells(const orc_system *s) { return (int64_t)s->grid[0] * s->grid[1] * s->grid[2]; }
 
-static int bead_type(const orc_system *s, int64_t chain, int i)
+/* Chain class: which block pattern a chain carries.  Chains start as
+ * [0, n_chains_a) -> a and the rest -> b; conversion zones change it. */
+static int chain_class(const orc_system *s, const orc_state *st, int64_t chain)
 {
-    return chain < s->n_chains_a ? s->pattern_a[i] : s->pattern_b[i];
+    if (st && st->chain_class) return st->chain_class[chain];
+    return chain < s->n_chains_a ? 0 : 1;
 }
+
+static int bead_type(const orc_system *s, const orc_state *st, int64_t chain, int i)
+{
+    return chain_class(s, st, chain) == 0 ? s->pattern_a[i] : s->pattern_b[i];
+}
+
+static int has_walls(const orc_system *s) { return s->wall[1] > s->wall[0]; }
 
 static double cell_edge(const orc_system *s, int d) { return s->box[d] / (double)s->grid[d]; }
 
@@ -228,7 +244,7 @@ void orc_density(const orc_system *s, const orc_state *st, uint32_t *counts)
     for (int64_t c = 0; c < s->n_chains; ++c)
         for (int i = 0; i < s->N; ++i) {
             int64_t b = c * s->N + i;
-            counts[(int64_t)bead_type(s, c, i) * M + cell_of(s, st, b)] += 1u;
+            counts[(int64_t)bead_type(s, st, c, i) * M + cell_of(s, st, b)] += 1u;
         }
 }
 
@@ -243,6 +259,19 @@ static double f_nb(const orc_system *s, double pa, double pb)
     return 0.5 * s->kappaN * inc * inc - 0.25 * s->chiN * (pa - pb) * (pa - pb);
 }
 
+/* Umbrella potential toward target concentration fields (Sec. 3.2,
+ * "Coupling": placed molecules are equilibrated under an umbrella
+ * potential).  Per cell (lambda/2) [(phiA - tA)^2 + (phiB - tB)^2], in the
+ * same units as f_nb, so its field is lambda (phi_t - t_t) / N. */
+static int has_umbrella(const orc_system *s) { return s->umb_lambda > 0.0 && s->umb_target != NULL; }
+
+static double f_umb(const orc_system *s, int64_t c, double pa, double pb)
+{
+    int64_t M = n_cells(s);
+    double da = pa - s->umb_target[c], db = pb - s->umb_target[M + c];
+    return 0.5 * s->umb_lambda * (da * da + db * db);
+}
+
 /* H_nb / kT of the whole system from the counts. */
 double orc_energy_nb(const orc_system *s, const uint32_t *counts)
 {
@@ -251,7 +280,9 @@ double orc_energy_nb(const orc_system *s, const uint32_t *counts)
     double phi_per_count = (double)M / B;
     double sum = 0.0, comp = 0.0;   /* Neumaier */
     for (int64_t c = 0; c < M; ++c) {
-        double v = f_nb(s, counts[c] * phi_per_count, counts[M + c] * phi_per_count);
+        double pa = counts[c] * phi_per_count, pb = counts[M + c] * phi_per_count;
+        double v = f_nb(s, pa, pb);
+        if (has_umbrella(s)) v += f_umb(s, c, pa, pb);
         double t = sum + v;
         if (fabs(sum) >= fabs(v)) comp += (sum - t) + v; else comp += (v - t) + sum;
         sum = t;
@@ -259,7 +290,7 @@ double orc_energy_nb(const orc_system *s, const uint32_t *counts)
     return (B / (double)M) / (double)s->N * (sum + comp);
 }
 
-/* omega[t * M + c] = dH_nb/dn_t(c) in kT. */
+/* omega[t * M + c] = dH/dn_t(c) in kT (non-bonded energy plus umbrella). */
 void orc_fields(const orc_system *s, const uint32_t *counts, double *omega)
 {
     int64_t M = n_cells(s);
@@ -274,6 +305,10 @@ void orc_fields(const orc_system *s, const uint32_t *counts, double *omega)
         } else {
             wa = inc - 0.5 * s->chiN * (pa - pb);
             wb = inc + 0.5 * s->chiN * (pa - pb);
+        }
+        if (has_umbrella(s)) {
+            wa += s->umb_lambda * (pa - s->umb_target[c]);
+            wb += s->umb_lambda * (pb - s->umb_target[M + c]);
         }
         omega[c] = wa / (double)s->N;
         omega[M + c] = wb / (double)s->N;
@@ -330,10 +365,48 @@ void orc_smc_draw(uint64_t seed, uint32_t sweep, uint32_t chain, uint32_t i, uin
 }
 
 /* ------------------------------------------------------------------------ */
+/* Boundary zones: molecular type conversion (Sec. 3.2, "Coupling")         */
+/* ------------------------------------------------------------------------ */
+static int has_zones(const orc_system *s) { return has_walls(s) && (s->zone[0] > 0 || s->zone[1] > 0); }
+
+/* Unwrapped z cell of bead b in the stored representation. */
+static int64_t z_cell(const orc_system *s, const orc_state *st, int64_t b)
+{
+    if (st->mode == 2) return st->cell[2 * n_beads(s) + b];
+    return ngp_index(s, 2, get_pos(s, st, 2, b));
+}
+
+/* After the moves of a sweep, a chain whose binned centre -- the mean of its
+ * beads' z-cell indexes -- lies in the lower conversion zone [wall[0],
+ * wall[0] + zone[0]) becomes a chain of pattern a; in the upper zone
+ * [wall[1] - zone[1], wall[1]) one of pattern b.  conv[] counts the
+ * conversions (the particle flux through each boundary zone).  The sum of
+ * integer indexes makes the decision exact. */
+void orc_convert(const orc_system *s, orc_state *st)
+{
+    if (!st->chain_class) return;
+    const int N = s->N;
+    const int64_t lo = (int64_t)N * (s->wall[0] + s->zone[0]);
+    const int64_t hi = (int64_t)N * (s->wall[1] - s->zone[1]);
+    for (int64_t c = 0; c < s->n_chains; ++c) {
+        int64_t sum = 0;
+        for (int i = 0; i < N; ++i) sum += z_cell(s, st, c * N + i);
+        if (s->zone[0] > 0 && sum < lo && st->chain_class[c] != 0) {
+            st->chain_class[c] = 0;
+            st->conv[0] += 1;
+        } else if (s->zone[1] > 0 && sum >= hi && st->chain_class[c] != 1) {
+            st->chain_class[c] = 1;
+            st->conv[1] += 1;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* One MC sweep with frozen fields                                           */
 /* ------------------------------------------------------------------------ */
 /* omega: [2][M] fields, read only during the sweep.  accepted: optional
- * per-bead decisions (1 accepted, 0 rejected).  Returns accepted count. */
+ * per-bead decisions (1 accepted, 0 rejected).  Returns accepted count.
+ * With conversion zones the sweep ends with the conversion step. */
 uint64_t orc_sweep(const orc_system *s, orc_state *st, uint64_t seed, uint32_t sweep,
                    const double *omega, uint8_t *accepted)
 {
@@ -421,16 +494,20 @@ uint64_t orc_sweep(const orc_system *s, orc_state *st, uint64_t seed, uint32_t s
 
                 /* Field energy change: omega of the bead's type at the new
                  * cell minus at the old cell. */
-                int t = bead_type(s, c, i);
+                int t = bead_type(s, st, c, i);
                 int64_t cell_old = cell_of(s, st, b);
                 /* cell of the proposal: evaluate it through a temporary state */
                 int64_t idx[3];
+                int outside = 0;
                 for (int a = 0; a < 3; ++a) {
                     int64_t ia;
                     if (st->mode == 2)
                         ia = c_new[a];
                     else
                         ia = ngp_index(s, a, r_new[a]);
+                    /* walls (Sec. 3.2, wall confinement): a trial position whose
+                     * z cell lies outside [wall[0], wall[1]) is rejected */
+                    if (a == 2 && has_walls(s) && (ia < s->wall[0] || ia >= s->wall[1])) outside = 1;
                     idx[a] = wrap_index(ia, s->grid[a]);
                 }
                 int64_t cell_new = (idx[0] * s->grid[1] + idx[1]) * s->grid[2] + idx[2];
@@ -448,7 +525,7 @@ uint64_t orc_sweep(const orc_system *s, orc_state *st, uint64_t seed, uint32_t s
                     dE -= (fwd - rev) / (4.0 * A);
                 }
 
-                int acc = u < exp(-dE);
+                int acc = !outside && u < exp(-dE);
                 if (accepted) accepted[b] = (uint8_t)acc;
                 if (acc) {
                     n_acc += 1;
@@ -466,6 +543,7 @@ uint64_t orc_sweep(const orc_system *s, orc_state *st, uint64_t seed, uint32_t s
             }
         }
     }
+    if (has_zones(s)) orc_convert(s, st);
     return n_acc;
 }
 
@@ -488,38 +566,197 @@ uint64_t orc_run(const orc_system *s, orc_state *st, uint64_t seed, uint32_t fir
 /* ------------------------------------------------------------------------ */
 /* Initial configuration: Gaussian random walks                              */
 /* ------------------------------------------------------------------------ */
-/* Bead 0 uniform in the box from the top 24 bits of words 0-2; every bond
- * component N(0, Re^2/(3(N-1))) by Box-Muller on words (0,1) and (2,3).
- * The counter's fourth word carries the system id with the top bit set, so
- * this stream never meets a move draw.  Written in FP64. */
-void orc_init_walks(const orc_system *s, uint64_t seed, double *xyz)
+/* Initial streams use counter word 3 = system id with the top bit set, so
+ * they never meet a move draw; counter word 2 names the stream and the
+ * attempt j (walls only): 4j initial walks, 4j + 1 placement targets,
+ * 4j + 2 placement walks. */
+static void init_block(const orc_system *s, uint64_t seed, uint32_t w0, uint32_t chain, uint32_t stream,
+                       uint32_t w[4])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {w0, chain, stream, s->sys_id | 0x80000000u};
+    orc_philox4x32_10(ctr, key, w);
+}
+
+static double top24(uint32_t w) { return (double)(w >> 8) * 0x1p-24; }
+
+/* One bond of a Gaussian walk: each component N(0, sigma^2) by Box-Muller
+ * on words (0,1) and (2,3). */
+static void gauss_bond(const uint32_t w[4], double sigma, double b[3])
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double u1 = ((double)(w[0] >> 8) + 0.5) * 0x1p-24;
+    double u2 = top24(w[1]);
+    double u3 = ((double)(w[2] >> 8) + 0.5) * 0x1p-24;
+    double u4 = top24(w[3]);
+    double rad1 = sqrt(-2.0 * log(u1)), rad2 = sqrt(-2.0 * log(u3));
+    b[0] = sigma * rad1 * cos(two_pi * u2);
+    b[1] = sigma * rad1 * sin(two_pi * u2);
+    b[2] = sigma * rad2 * cos(two_pi * u4);
+}
+
+#define ORC_MAX_ATTEMPTS 64
+
+/* Walls: a generated chain is kept only if every bead's z lies in
+ * [wall[0] e + e/128, wall[1] e - e/128] (e the FP32 cell edge): a margin of
+ * 1/128 edge keeps the stored representation's z cell inside the walls
+ * whatever the rounding (|z| < 2^15 edges).  Otherwise the chain is drawn
+ * again from the next attempt's counters. */
+static int chain_fits(const orc_system *s, const double *z, int N)
+{
+    if (!has_walls(s)) return 1;
+    double e = (double)(float)cell_edge(s, 2);
+    double lo = (double)s->wall[0] * e + e / 128.0, hi = (double)s->wall[1] * e - e / 128.0;
+    for (int i = 0; i < N; ++i)
+        if (!(z[i] >= lo && z[i] <= hi)) return 0;
+    return 1;
+}
+
+/* Bead 0 uniform in the box (in z between the walls when there are walls)
+ * from the top 24 bits of words 0-2; every bond component
+ * N(0, Re^2/(3(N-1))).  Written in FP64.  Returns 0, or -2 when a chain did
+ * not fit between the walls in ORC_MAX_ATTEMPTS attempts. */
+int orc_init_walks(const orc_system *s, uint64_t seed, double *xyz)
 {
     const int64_t B = n_beads(s);
-    const double sigma = s->Re / sqrt(3.0 * (double)(s->N > 1 ? s->N - 1 : 1));
-    const double two_pi = 6.283185307179586476925286766559;
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    for (int64_t c = 0; c < s->n_chains; ++c) {
-        double r[3];
-        for (int i = 0; i < s->N; ++i) {
-            uint32_t ctr[4] = {(uint32_t)i, (uint32_t)c, 0u, s->sys_id | 0x80000000u};
-            uint32_t w[4];
-            orc_philox4x32_10(ctr, key, w);
-            if (i == 0) {
-                for (int a = 0; a < 3; ++a)
-                    r[a] = s->box[a] * ((double)(w[a] >> 8) * 0x1p-24);
-            } else {
-                double u1 = ((double)(w[0] >> 8) + 0.5) * 0x1p-24;
-                double u2 = (double)(w[1] >> 8) * 0x1p-24;
-                double u3 = ((double)(w[2] >> 8) + 0.5) * 0x1p-24;
-                double u4 = (double)(w[3] >> 8) * 0x1p-24;
-                double rad1 = sqrt(-2.0 * log(u1)), rad2 = sqrt(-2.0 * log(u3));
-                r[0] += sigma * rad1 * cos(two_pi * u2);
-                r[1] += sigma * rad1 * sin(two_pi * u2);
-                r[2] += sigma * rad2 * cos(two_pi * u4);
+    const int N = s->N;
+    const double sigma = s->Re / sqrt(3.0 * (double)(N > 1 ? N - 1 : 1));
+    double *r = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    int rc = 0;
+    for (int64_t c = 0; c < s->n_chains && rc == 0; ++c) {
+        int ok = 0;
+        for (int j = 0; j < ORC_MAX_ATTEMPTS && !ok; ++j) {
+            for (int i = 0; i < N; ++i) {
+                uint32_t w[4];
+                init_block(s, seed, (uint32_t)i, (uint32_t)c, 4u * (uint32_t)j, w);
+                if (i == 0) {
+                    for (int a = 0; a < 3; ++a) r[a * N] = s->box[a] * top24(w[a]);
+                    if (has_walls(s)) {
+                        double e = (double)(float)cell_edge(s, 2);
+                        double lo = (double)s->wall[0] * e, hi = (double)s->wall[1] * e;
+                        r[2 * N] = lo + (hi - lo) * top24(w[2]);
+                    }
+                } else {
+                    double b[3];
+                    gauss_bond(w, sigma, b);
+                    for (int a = 0; a < 3; ++a) r[a * N + i] = r[a * N + i - 1] + b[a];
+                }
             }
-            for (int a = 0; a < 3; ++a) xyz[a * B + c * s->N + i] = r[a];
+            ok = chain_fits(s, r + 2 * N, N);
+        }
+        if (!ok) rc = -2;
+        for (int a = 0; a < 3; ++a)
+            for (int i = 0; i < N; ++i) xyz[a * B + c * N + i] = r[a * N + i];
+    }
+    free(r);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Placement from target concentration fields (Sec. 3.2, "Coupling")        */
+/* ------------------------------------------------------------------------ */
+/* Each molecule is placed within half a mean end-to-end distance of a
+ * target position that follows the supplied concentration fields:
+ *   1. chains of class k (pattern a or b, with A fraction f_k) draw a target
+ *      cell with probability proportional to the integer weight
+ *      w_k(c) = floor(2^20 (f_k tA(c) + (1 - f_k) tB(c)) + 1/2), through the
+ *      exact inclusive prefix sum W_k: the cell is the first c with
+ *      W_k(c) > t, t = floor(v T_k / 2^64), v the 64-bit word (w0 << 32 | w1)
+ *      of block (0, chain, 4j + 1) and T_k the total weight;
+ *   2. the target point is uniform in that cell (words w2, w3 of that block
+ *      and w0 of block (1, chain, 4j + 1));
+ *   3. the chain's centre of mass goes uniformly into the ball of radius
+ *      Re/2 around it: radius (Re/2) cbrt(u1), cos(theta) = 2 u2 - 1,
+ *      azimuth 2 pi u3 (words w1-w3 of block (1, chain, 4j + 1));
+ *   4. the conformation is a Gaussian walk (bonds from blocks
+ *      (i, chain, 4j + 2)), shifted to that centre.
+ * t_k = umb_target ([2][M]).  targets (or NULL): [3][n_chains] target points;
+ * cells (or NULL): [n_chains] target cells.  Returns 0, -1 for a negative
+ * or non-finite target or a class with zero total weight, -2 when a chain
+ * did not fit between the walls in ORC_MAX_ATTEMPTS attempts. */
+int orc_place_from_fields(const orc_system *s, const orc_state *st, uint64_t seed, double *xyz, double *targets,
+                          int64_t *cells)
+{
+    const int64_t B = n_beads(s), M = n_cells(s);
+    const int N = s->N;
+    const double sigma = s->Re / sqrt(3.0 * (double)(N > 1 ? N - 1 : 1));
+    const double two_pi = 6.283185307179586476925286766559;
+    if (!s->umb_target) return -1;
+    for (int64_t c = 0; c < 2 * M; ++c)
+        if (!(s->umb_target[c] >= 0.0 && s->umb_target[c] <= 4096.0)) return -1;
+    uint64_t *W = (uint64_t *)malloc(sizeof(uint64_t) * 2 * (size_t)M);
+    double *r = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    for (int k = 0; k < 2; ++k) {
+        const uint8_t *pat = k == 0 ? s->pattern_a : s->pattern_b;
+        int na = 0;
+        for (int i = 0; i < N; ++i) na += pat[i] == 0;
+        double fa = (double)na / (double)N, fb = (double)(N - na) / (double)N;
+        uint64_t run = 0;
+        for (int64_t c = 0; c < M; ++c) {
+            double v = fa * s->umb_target[c] + fb * s->umb_target[M + c];
+            run += (uint64_t)floor(1048576.0 * v + 0.5);
+            W[k * M + c] = run;
         }
     }
+    int rc = 0;
+    for (int64_t ch = 0; ch < s->n_chains && rc == 0; ++ch) {
+        const int k = chain_class(s, st, ch);
+        const uint64_t *Wk = W + k * M;
+        const uint64_t T = Wk[M - 1];
+        if (T == 0) { rc = -1; break; }
+        int ok = 0;
+        double tp[3] = {0, 0, 0};
+        int64_t cell = 0;
+        for (int j = 0; j < ORC_MAX_ATTEMPTS && !ok; ++j) {
+            uint32_t w[4], q[4];
+            init_block(s, seed, 0u, (uint32_t)ch, 4u * (uint32_t)j + 1u, w);
+            init_block(s, seed, 1u, (uint32_t)ch, 4u * (uint32_t)j + 1u, q);
+            uint64_t v = ((uint64_t)w[0] << 32) | w[1];
+            uint64_t t = (uint64_t)(((unsigned __int128)v * T) >> 64);
+            int64_t lo = 0, hi = M - 1;          /* first c with Wk[c] > t */
+            while (lo < hi) {
+                int64_t mid = lo + (hi - lo) / 2;
+                if (Wk[mid] > t) hi = mid; else lo = mid + 1;
+            }
+            cell = lo;
+            int64_t ix = cell / ((int64_t)s->grid[1] * s->grid[2]);
+            int64_t iy = (cell / s->grid[2]) % s->grid[1];
+            int64_t iz = cell % s->grid[2];
+            double u3[3] = {top24(w[2]), top24(w[3]), top24(q[0])};
+            int64_t ic[3] = {ix, iy, iz};
+            for (int a = 0; a < 3; ++a) tp[a] = ((double)ic[a] + u3[a]) * cell_edge(s, a);
+            double rad = 0.5 * s->Re * cbrt(top24(q[1]));
+            double ct = 2.0 * top24(q[2]) - 1.0;
+            double stt = sqrt(fmax(0.0, 1.0 - ct * ct));
+            double ph = two_pi * top24(q[3]);
+            double centre[3] = {tp[0] + rad * stt * cos(ph), tp[1] + rad * stt * sin(ph), tp[2] + rad * ct};
+            double com[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a) r[a * N] = 0.0;
+            for (int i = 1; i < N; ++i) {
+                uint32_t g[4];
+                double b[3];
+                init_block(s, seed, (uint32_t)i, (uint32_t)ch, 4u * (uint32_t)j + 2u, g);
+                gauss_bond(g, sigma, b);
+                for (int a = 0; a < 3; ++a) r[a * N + i] = r[a * N + i - 1] + b[a];
+            }
+            for (int a = 0; a < 3; ++a) {
+                for (int i = 0; i < N; ++i) com[a] += r[a * N + i];
+                com[a] /= (double)N;
+            }
+            for (int a = 0; a < 3; ++a)
+                for (int i = 0; i < N; ++i) r[a * N + i] = centre[a] + (r[a * N + i] - com[a]);
+            ok = chain_fits(s, r + 2 * N, N);
+        }
+        if (!ok) { rc = -2; break; }
+        for (int a = 0; a < 3; ++a)
+            for (int i = 0; i < N; ++i) xyz[a * B + ch * N + i] = r[a * N + i];
+        if (targets)
+            for (int a = 0; a < 3; ++a) targets[a * s->n_chains + ch] = tp[a];
+        if (cells) cells[ch] = cell;
+    }
+    free(W);
+    free(r);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -58,6 +58,8 @@ class SystemDesc:
     ham_form: int = 0              # 0: Helfand form, 1: chiN*phiA*phiB form
     label: str = ""
     smc_A: float = 0.0             # > 0: bond-force-biased moves with this A (Re^2); 0: uniform moves
+    walls: Optional[tuple] = None  # (lo, hi): hard walls at these z-cell faces; None: periodic z
+    zones: Optional[tuple] = None  # (lower, upper): z-cell widths of the conversion zones at the walls
 
     @property
     def n_beads(self) -> int:

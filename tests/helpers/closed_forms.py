@@ -9,6 +9,8 @@ pair_weight_1d: sum over periodic images of the double integral of the bond
   weight exp(-(k/2)(x-y)^2) over two grid cells, by the erf antiderivative.
 two_bead_cell_probabilities: exact joint cell occupancy of a two-bead chain
   (A-B) with harmonic bond k in frozen fields omega_A, omega_B.
+two_bead_cell_probabilities_walls: the same with hard walls at the z-cell
+  faces lo and hi (no periodic images in z, zero weight outside).
 """
 import math
 
@@ -48,6 +50,27 @@ def pair_weight_1d(n, L, k, n_images=6):
                 tot += G2(hi1 - lo2) - G2(hi1 - hi2) - G2(lo1 - lo2) + G2(lo1 - hi2)
             Wm[i, j] = tot
     return Wm
+
+
+def pair_weight_1d_open(n, L, k):
+    """Double integral of exp(-(k/2)(x-y)^2) over two cells of an open
+    (non-periodic) line: the m = 0 image of pair_weight_1d."""
+    return pair_weight_1d(n, L, k, n_images=0)
+
+
+def two_bead_cell_probabilities_walls(omega, n, L, k, lo, hi):
+    """P[c1, c2] for a cubic grid n^3 with periodic x and y and hard walls at
+    the z-cell faces lo < hi: both beads confined to z cells [lo, hi)."""
+    M = n ** 3
+    Wx = pair_weight_1d(n, L, k)
+    Wz = pair_weight_1d_open(n, L, k)
+    idx = np.array(np.unravel_index(np.arange(M), (n, n, n)))
+    inside = (idx[2] >= lo) & (idx[2] < hi)
+    Wpair = Wx[idx[0][:, None], idx[0][None, :]] * Wx[idx[1][:, None], idx[1][None, :]] \
+        * Wz[idx[2][:, None], idx[2][None, :]]
+    Wpair = Wpair * inside[:, None] * inside[None, :]
+    P = np.exp(-omega[0])[:, None] * np.exp(-omega[1])[None, :] * Wpair
+    return P / P.sum(), idx
 
 
 def two_bead_cell_probabilities(omega, n, L, k):
