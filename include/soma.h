@@ -77,10 +77,25 @@ enum { SOMA_HAM_HELFAND = 0, SOMA_HAM_CHI_AB = 1 };
 /* One independent system.  Chains [0, n_chains_a) carry the bead types of
  * pattern_a, chains [n_chains_a, n_chains) those of pattern_b (0 = A,
  * 1 = B): a diblock or triblock melt sets n_chains_a = n_chains, an A/B
- * homopolymer blend an all-A pattern_a and an all-B pattern_b.
+ * homopolymer blend an all-A pattern_a and an all-B pattern_b.  A chain's
+ * pattern is its class (a or b); boundary zones and soma_set_classes change
+ * classes.
  * Limits: 2 <= N <= 128; 1 <= grid[d] <= 32768 with grid[0] * grid[1] <= 2^24;
  * move_halfwidth below 0.99 cell edges box[d]/grid[d]; smc_A zero, or
- * positive with sqrt(2 smc_A) at most half a cell edge. */
+ * positive with sqrt(2 smc_A) at most half a cell edge.
+ *
+ * Walls and boundary zones (Sec. 3.2, "Coupling": the SOMA subdomain keeps
+ * fixed boundary fluxes by wall confinement and converts molecules in
+ * boundary zones): walls = {lo, hi} with 0 <= lo < hi <= grid[2] puts hard
+ * walls at the z-cell faces lo and hi -- a trial move whose z cell leaves
+ * [lo, hi) is rejected, and initial walks and placements draw chains again
+ * until every bead lies between the walls (64 attempts, else SOMA_EINVAL);
+ * {0, 0} means periodic z.  zones = {w_lo, w_hi} (cells, with walls only,
+ * lo + w_lo <= hi - w_hi) are conversion zones at the walls: after the moves
+ * of every sweep a chain whose mean z-cell index is below lo + w_lo becomes
+ * class a, at or above hi - w_hi class b; soma_observables counts the
+ * conversions (the molecular flux through each zone).  Systems with zones
+ * need density mode 0 or 1 (a conversion changes a cell's species). */
 typedef struct {
     int32_t n_chains;
     int32_t N;                 /* beads per chain */
@@ -99,6 +114,8 @@ typedef struct {
                                   normal), accepted with the Metropolis-Hastings ratio of the
                                   Gaussian proposal densities; a displacement of 0.99 cell edges
                                   or more is rejected.  Requires sqrt(2A) <= 0.5 cell edge. */
+    int32_t walls[2];          /* z-cell faces of the walls {lo, hi}; {0, 0}: periodic z */
+    int32_t zones[2];          /* widths in z cells of the conversion zones at the lower and upper wall */
 } soma_system_desc;
 
 typedef struct {
@@ -125,6 +142,9 @@ typedef struct {
     int32_t launch_order;      /* 0: workgroups remapped so that each XCD gets a contiguous
                                   tile range; 1: tiles in launch order */
     void *hip_stream;          /* hipStream_t, NULL for the null stream */
+    int32_t coupling;          /* nonzero: reserve workspace for target concentration fields
+                                  (soma_place_from_fields, soma_set_umbrella): 8 B per cell
+                                  plus 16 B per cell of the largest system */
 } soma_options;
 
 typedef struct {
@@ -136,6 +156,8 @@ typedef struct {
                                   (a resumed checkpoint counts from the resume) */
     uint64_t n_moves, n_accepted;
     uint64_t sweep;            /* sweeps done since creation */
+    uint64_t converted_to_a;   /* chains converted to class a in the lower zone since creation */
+    uint64_t converted_to_b;   /* chains converted to class b in the upper zone since creation */
 } soma_obs;
 
 typedef struct {
@@ -243,6 +265,37 @@ int soma_set_fields(soma_ctx *ctx, int32_t sys, const float *omega);
 /* Return system `sys` to fields derived from its density each sweep. */
 int soma_release_fields(soma_ctx *ctx, int32_t sys);
 
+/* Place the chains of system `sys` so that they reproduce target
+ * concentration fields, the start of a SOMA run in the coupled workflow
+ * (Sec. 3.2, "Coupling": molecules are placed within half a mean
+ * end-to-end distance of their target positions).  phi_target: host float
+ * [2][nx][ny][nz] (phi_A then phi_B, each in [0, 4096]).  A chain of class k
+ * (A fraction f_k of its pattern) draws a target cell with probability
+ * proportional to the integer weight floor(2^20 (f_k phi_A + (1 - f_k) phi_B)
+ * + 1/2) through an exact inverse prefix sum, a target point uniform in the
+ * cell, its centre of mass uniform in the ball of radius Re/2 around that
+ * point, and a Gaussian-walk conformation (Philox streams of the initial
+ * configuration).  The targets stay on the device for soma_set_umbrella;
+ * the density is rebuilt.  Needs opts.coupling.  SOMA_EINVAL for a bad
+ * value, for a class with chains but zero total weight, or when chains do not
+ * fit between the walls (which latches the context). */
+int soma_place_from_fields(soma_ctx *ctx, int32_t sys, const float *phi_target);
+
+/* Umbrella potential toward the target fields of soma_place_from_fields,
+ * used to equilibrate the placed molecules (Sec. 3.2, "Coupling"): adds
+ * (lambda/2) sum_cells sum_t (phi_t - target_t)^2, in the units of H_nb, to
+ * the energy, so omega_t gains lambda (phi_t - target_t) / N.  lambda >= 0;
+ * 0 switches it off.  Applies to fields derived from the counts (not to
+ * frozen fields).  SOMA_EINVAL for a bad lambda or no stored target. */
+int soma_set_umbrella(soma_ctx *ctx, int32_t sys, double lambda);
+
+/* Chain classes of system `sys` in logical chain order (host uint8
+ * [n_chains], 0 = pattern_a, 1 = pattern_b), for checkpoints of runs with
+ * conversion zones.  soma_set_classes rebuilds the density and makes the
+ * classes authoritative for the system. */
+int soma_get_classes(soma_ctx *ctx, int32_t sys, uint8_t *cls);
+int soma_set_classes(soma_ctx *ctx, int32_t sys, const uint8_t *cls);
+
 /* Set the sweep counter (the Philox counter word of the next sweep) for a
  * resumed checkpoint, and rebuild every system's density for it. */
 int soma_set_sweep(soma_ctx *ctx, uint64_t sweep);
@@ -265,10 +318,35 @@ typedef struct {
     int32_t xcd_remap;
     int32_t density_mode;      /* chosen density update */
     int32_t n_candidates;
-    double us_per_sweep;       /* trial time of the chosen shape */
-    double us_per_sweep_before;/* trial time of the shape in use at the call */
+    double us_per_sweep;       /* trial time of the chosen shape (0 when from_cache) */
+    double us_per_sweep_before;/* trial time of the shape in use at the call (0 when from_cache) */
+    int32_t from_cache;        /* 1: the shape came from the process-wide cache, nothing was timed */
 } soma_tune;
 int soma_autotune(soma_ctx *ctx, int32_t trial_sweeps, soma_tune *out);
+
+/* Empty the process-wide autotune cache.  soma_autotune first looks up the
+ * context's key -- representation, count width, move kinds, graph use,
+ * reorder on/off, compute units, and buckets of the number of systems (1,
+ * 2-16, 17-128, more), of the total bead count (powers of two) and of the
+ * largest and the bead-weighted mean chain length (16, 32, 64, 128) -- and
+ * applies a cached shape without timing; otherwise it tunes and stores the
+ * result.  Thread-safe. */
+void soma_tune_cache_clear(void);
+
+/* Per-kernel durations, the launch-configuration evidence of Sec. 2.2's
+ * profiling: runs n_sweeps (1..1000) real sweeps -- they advance the
+ * trajectory exactly like soma_mc_sweep -- launched eagerly with HIP events
+ * on the context's stream before and after each sweep kernel and after each
+ * fold kernel, and reports the average durations.  Synchronises.
+ * SOMA_EINVAL for a bad count or a null out. */
+typedef struct {
+    int32_t n_sweeps;
+    int32_t density_mode;      /* the density update in use */
+    double sweep_kernel_us;    /* k_sweep: moves and the density delta */
+    double fold_kernel_us;     /* the fold after it (0 launches in density mode 1) */
+    double sweep_us;           /* their sum */
+} soma_ktimes;
+int soma_time_kernels(soma_ctx *ctx, int32_t n_sweeps, soma_ktimes *out);
 
 /* Text of the last error of ctx (or of the last failed soma_create when
  * ctx is NULL).  Valid until the next call on the context. */

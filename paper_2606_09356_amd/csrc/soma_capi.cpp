@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -27,7 +28,8 @@ thread_local std::string g_create_error;
 
 struct Layout {
     size_t systems, tiles, chain_id, chain_id2, P[3], C[3], Q[3], D[3], keys, hist, bsum, perm, base, delta, flux, chunks,
-        omega, accept, status, partials, obs_out, staging, total;   // base: counts, delta: density delta
+        omega, accept, status, partials, obs_out, staging, chain_class, chain_class2, conv, tgt, place_W, place_bsum,
+        total;   // base: counts, delta: density delta
     int64_t total_slots = 0, total_cells = 0, total_chains = 0, count_words = 0;
     int n_tiles = 0;
     int n_chunks = 0;      // fold chunks of density mode 2
@@ -39,7 +41,15 @@ struct HostSys {
     std::vector<uint8_t> pa, pb;
     DevSys dev;
     int tile_begin, tile_end;
+    bool has_target = false;   // soma_place_from_fields stored target fields
+    double umb_lambda = 0.0;
+    bool cls_weight[2] = {false, false};
 };
+
+// Process-wide cache of autotuned launch shapes, keyed by the properties
+// of a context that decide its best shape (see tune_key).
+std::mutex g_tune_mu;
+std::map<std::string, soma_tune> g_tune_cache;
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 inline int64_t align64(int64_t v) { return (v + 63) & ~int64_t(63); }
@@ -65,6 +75,7 @@ struct soma_ctx {
     bool flux_dirty = false;
     uint64_t flux_sweep = 0;
     int any_smc = 0;       // some system moves with bond-force-biased moves
+    int any_zones = 0;     // some system has conversion zones (density mode 2 excluded)
     uint64_t sweep = 0;
     // sweeps run on this context (the acceptance counters count their moves);
     // unlike `sweep` it is not moved by soma_set_sweep
@@ -98,6 +109,10 @@ struct soma_ctx {
     double *partials() const { return reinterpret_cast<double *>(ws + L.partials); }
     double *obs_out() const { return reinterpret_cast<double *>(ws + L.obs_out); }
     void *staging() const { return ws + L.staging; }
+    uint8_t *chain_class() const { return reinterpret_cast<uint8_t *>(ws + L.chain_class); }
+    uint8_t *chain_class2() const { return reinterpret_cast<uint8_t *>(ws + L.chain_class2); }
+    unsigned long long *conv() const { return reinterpret_cast<unsigned long long *>(ws + L.conv); }
+    float2 *tgt() const { return L.tgt ? reinterpret_cast<float2 *>(ws + L.tgt) : nullptr; }
     int64_t words_per_cell() const { return cw == soma::COUNT_U16 ? 1 : 2; }
 };
 
@@ -163,6 +178,14 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
                 return bad("smc_A must be 0 or positive with sqrt(2 smc_A) <= 0.5 cell edge");
         }
         if (cells >= (int64_t(1) << 31)) return bad("too many cells");
+        const bool walls = d.walls[0] != 0 || d.walls[1] != 0;
+        if (walls && !(d.walls[0] >= 0 && d.walls[0] < d.walls[1] && d.walls[1] <= d.grid[2]))
+            return bad("walls must satisfy 0 <= lo < hi <= grid[2] (or be {0, 0})");
+        if (d.zones[0] < 0 || d.zones[1] < 0) return bad("zone widths must be >= 0");
+        if ((d.zones[0] > 0 || d.zones[1] > 0) && !walls) return bad("conversion zones need walls");
+        if (walls && d.walls[0] + d.zones[0] > d.walls[1] - d.zones[1]) return bad("conversion zones overlap");
+        if ((d.zones[0] > 0 || d.zones[1] > 0) && opt->density_mode == 2)
+            return bad("conversion zones need density mode 0 or 1");
         if ((int64_t)d.grid[0] * d.grid[1] > (int64_t(1) << 24)) return bad("grid[0] * grid[1] must be <= 2^24");
     }
     // count words and chains are indexed with 32-bit values across the batch
@@ -177,6 +200,8 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
     if (chains >= (int64_t(1) << 31)) { msg = "the systems' chains exceed 2^31 in total"; return SOMA_EINVAL; }
     return SOMA_OK;
 }
+
+void set_field_coefs(HostSys &h);
 
 Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt, std::vector<HostSys> *out)
 {
@@ -231,25 +256,22 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
             for (int a = 0; a < 3; ++a) v.dmax[a] = (float)(0.99 * (d.box[a] / d.grid[a]));
             v.delta = (float)d.move_halfwidth;
             v.inv_P = (float)(1.0 / P);
-            const double s = (double)M / ((double)d.n_chains * d.N);   // phi per count
-            const double inv_n = 1.0 / d.N;
-            if (d.ham_form == SOMA_HAM_HELFAND) {
-                v.cAA = (float)(s * (d.kappaN - 0.5 * d.chiN) * inv_n);
-                v.cAB = (float)(s * (d.kappaN + 0.5 * d.chiN) * inv_n);
-                v.cBA = v.cAB;
-                v.cBB = v.cAA;
-            } else {
-                v.cAA = (float)(s * d.kappaN * inv_n);
-                v.cAB = (float)(s * (d.kappaN + d.chiN) * inv_n);
-                v.cBA = v.cAB;
-                v.cBB = v.cAA;
-            }
-            v.c0 = (float)(-d.kappaN * inv_n);
             v.n_cells = M;
+            v.umb = 0;
+            v.walls = (d.walls[0] != 0 || d.walls[1] != 0) ? 1 : 0;
+            v.wall_lo = d.walls[0];
+            v.wall_hi = d.walls[1];
+            v.zones = (d.zones[0] > 0 || d.zones[1] > 0) ? 1 : 0;
+            v.cls_array = v.zones;
+            v.zone_a = d.zones[0] > 0;
+            v.zone_b = d.zones[1] > 0;
+            v.zone_a_lim = d.N * (d.walls[0] + d.zones[0]);
+            v.zone_b_lim = d.N * (d.walls[1] - d.zones[1]);
             for (int i = 0; i < d.N; ++i) {
                 if (h.pa[i]) v.pat_a[i >> 5] |= 1u << (i & 31);
                 if (h.pb[i]) v.pat_b[i >> 5] |= 1u << (i & 31);
             }
+            set_field_coefs(h);
             h.tile_begin = tiles;
             h.tile_end = tiles + nt;
             out->push_back(std::move(h));
@@ -302,6 +324,16 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     L.partials = take(sizeof(double) * 12 * max_blocks);
     L.obs_out = take(sizeof(double) * 8);
     L.staging = take(sizeof(float) * 2 * max_cells);
+    L.chain_class = take(sizeof(uint8_t) * chains);
+    L.chain_class2 = take(sizeof(uint8_t) * chains);     // autotune save
+    L.conv = take(sizeof(uint64_t) * 2 * n_sys);
+    if (opt->coupling) {
+        L.tgt = take(sizeof(float) * 2 * cells);
+        L.place_W = take(sizeof(uint64_t) * 2 * max_cells);
+        L.place_bsum = take(sizeof(uint64_t) * soma::place_bsum_words(max_cells));
+    } else {
+        L.tgt = L.place_W = L.place_bsum = 0;
+    }
     L.total = off;
     return L;
 }
@@ -328,6 +360,7 @@ int sync_status(soma_ctx *c)
     if (st & soma::ST_COUNT_OVERFLOW) { c->latched = SOMA_EOVERFLOW; return fail(c, SOMA_EOVERFLOW, "density count exceeded its width"); }
     if (st & soma::ST_CELL_OVERFLOW) { c->latched = SOMA_EOVERFLOW; return fail(c, SOMA_EOVERFLOW, "bead cell index left the int32 range (or a coordinate is not finite)"); }
     if (st & soma::ST_INTERNAL) { c->latched = SOMA_EDEVICE; return fail(c, SOMA_EDEVICE, "internal consistency check failed in the chain reorder"); }
+    if (st & soma::ST_PLACEMENT) { c->latched = SOMA_EINVAL; return fail(c, SOMA_EINVAL, "chains do not fit between the walls (64 attempts each)"); }
     return SOMA_OK;
 }
 
@@ -341,6 +374,34 @@ void set_shape(soma_ctx *c, int waves_per_block, int waves_per_cu, int xcd_remap
     c->max_blocks = waves_per_cu > 0 ? std::max(1, waves_per_cu * c->n_cus / waves_per_block) : 0;
 }
 
+// Key of the autotune cache: representation, count width, move kinds,
+// graph use, reorder, compute units, and buckets of the batch -- number of
+// systems (1, 2-16, 17-128, more), total beads (powers of two) and the
+// largest and bead-weighted mean chain length (16, 32, 64, 128).
+std::string tune_key(const soma_ctx *c)
+{
+    int64_t beads = 0;
+    double nsum = 0.0;
+    int nmax = 0;
+    for (const HostSys &h : c->sys) {
+        const int64_t b = (int64_t)h.d.n_chains * h.d.N;
+        beads += b;
+        nsum += (double)b * h.d.N;
+        nmax = std::max(nmax, h.d.N);
+    }
+    auto nb = [](double n) { return n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 128; };
+    const int ns = (int)c->sys.size();
+    const int sb = ns == 1 ? 0 : ns <= 16 ? 1 : ns <= 128 ? 2 : 3;
+    int lb = 0;
+    while ((int64_t(1) << (lb + 1)) <= beads) ++lb;
+    char b[200];
+    std::snprintf(b, sizeof b, "r%d c%d s%d z%d g%d o%d cu%d n%d b%d nmax%d nmean%d", c->repr, c->cw, c->any_smc,
+                  c->any_zones,
+                  c->opt.use_graph ? 1 : 0, c->opt.reorder_every > 0 ? 1 : 0, c->n_cus, sb, lb, nb(nmax),
+                  nb(nsum / (double)std::max<int64_t>(beads, 1)));
+    return b;
+}
+
 // Captured graphs hold the launch shape in their kernel nodes.
 void drop_graphs(soma_ctx *c)
 {
@@ -348,6 +409,15 @@ void drop_graphs(soma_ctx *c)
     for (hipGraph_t g : c->graph_defs) (void)hipGraphDestroy(g);
     c->graphs.clear();
     c->graph_defs.clear();
+}
+
+// Some system needs the coupling code of the sweep kernel (walls, zones,
+// umbrella, or chain classes from the class array).
+int any_coupling(const soma_ctx *c)
+{
+    for (const HostSys &h : c->sys)
+        if (h.dev.walls || h.dev.zones || h.dev.umb || h.dev.cls_array) return 1;
+    return 0;
 }
 
 soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
@@ -370,12 +440,16 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
     a.density_mode = c->density_mode;
     a.flux = c->flux();
     a.smc = c->any_smc;
+    a.cpl = any_coupling(c);
     a.omega = c->omega();
     a.sweep_ctr = c->sweep_ctr();
     a.rel = rel;
     a.seed = c->opt.seed;
     a.accept = c->accept();
     a.status = c->status();
+    a.chain_class = c->chain_class();
+    a.tgt = c->tgt();
+    a.conv = c->conv();
     return a;
 }
 
@@ -450,8 +524,80 @@ int rebuild_density(soma_ctx *c, int32_t sys)
     d.counts = cur;
     d.chain_id = c->chain_id();
     d.status = c->status();
+    d.chain_class = c->chain_class();
     HIPCHK(c, soma::launch_density(c->repr, c->cw, d, c->stream));
     return SOMA_OK;
+}
+
+// Arguments of the initial walks and of the placement of one system.
+soma::InitArgs init_args(const soma_ctx *c, const HostSys &h)
+{
+    soma::InitArgs ia{};
+    ia.repr = c->repr;
+    ia.n_chains = h.d.n_chains;
+    ia.N = h.d.N;
+    ia.stride = 2 * h.dev.P;
+    ia.slot_off = h.dev.slot_off;
+    ia.sys_id = h.dev.sys_id;
+    ia.seed = c->opt.seed;
+    for (int a = 0; a < 3; ++a) {
+        ia.box[a] = h.d.box[a];
+        ia.edge[a] = h.dev.edge[a];
+        (&ia.P0)[a] = c->P(a);
+        (&ia.C0)[a] = c->C(a);
+    }
+    ia.sigma = h.d.Re / std::sqrt(3.0 * (h.d.N - 1));
+    ia.walls = h.dev.walls;
+    ia.wall_lo = h.dev.wall_lo;
+    ia.wall_hi = h.dev.wall_hi;
+    ia.status = c->status();
+    return ia;
+}
+
+// Field coefficients of a system: omega_A = cAA nA + cAB nB + c0 and
+// omega_B = cBA nA + cBB nB + c0 (the umbrella's lambda phi_t / N included;
+// its -lambda target_t / N is added per cell by the kernels).
+void set_field_coefs(HostSys &h)
+{
+    const soma_system_desc &d = h.d;
+    DevSys &v = h.dev;
+    const double s = (double)v.n_cells / ((double)d.n_chains * d.N);   // phi per count
+    const double inv_n = 1.0 / d.N;
+    double aa, ab;
+    if (d.ham_form == SOMA_HAM_HELFAND) {
+        aa = s * (d.kappaN - 0.5 * d.chiN) * inv_n;
+        ab = s * (d.kappaN + 0.5 * d.chiN) * inv_n;
+    } else {
+        aa = s * d.kappaN * inv_n;
+        ab = s * (d.kappaN + d.chiN) * inv_n;
+    }
+    const double lam = v.umb ? h.umb_lambda : 0.0;
+    v.cAA = (float)(aa + s * lam * inv_n);
+    v.cBB = v.cAA;
+    v.cAB = (float)ab;
+    v.cBA = v.cAB;
+    v.c0 = (float)(-d.kappaN * inv_n);
+    v.umb_coef = (float)(lam * inv_n);
+}
+
+// floor(z / e) of an FP32 coordinate for the FP32 edge e, exact (FP64
+// products of a 24-bit edge and integers below 2^29 are exact).
+int z_floor(float z, float e)
+{
+    const double x = (double)z, ed = (double)e;
+    double k = std::floor(x / ed);
+    while (k * ed > x) k -= 1.0;
+    while ((k + 1.0) * ed <= x) k += 1.0;
+    return (int)std::max(-2147483647.0, std::min(2147483647.0, k));
+}
+
+// The walls must hold every bead of a system set from the host.
+bool inside_walls(const HostSys &h, const std::vector<int> &zc)
+{
+    if (!h.dev.walls) return true;
+    for (int v : zc)
+        if (v < h.dev.wall_lo || v >= h.dev.wall_hi) return false;
+    return true;
 }
 
 int upload_sys(soma_ctx *c, int32_t sys)
@@ -502,11 +648,16 @@ int reorder_chains(soma_ctx *c)
     return SOMA_OK;
 }
 
-int record_sweeps(soma_ctx *c, int32_t n, hipStream_t st)
+// Enqueue n sweeps on stream st.  With ev (3 events per sweep), sweep r
+// records ev[3r] before its sweep kernel, ev[3r+1] after it and ev[3r+2]
+// after its fold kernel (eager launches only: soma_time_kernels).
+int record_sweeps(soma_ctx *c, int32_t n, hipStream_t st, hipEvent_t *ev = nullptr)
 {
     for (int32_t r = 0; r < n; ++r) {
         soma::SweepArgs a = sweep_args(c, (uint32_t)r);
+        if (ev) HIPCHK(c, hipEventRecord(ev[3 * r], st));
         HIPCHK(c, soma::launch_sweep(c->repr, c->cw, a, st));
+        if (ev) HIPCHK(c, hipEventRecord(ev[3 * r + 1], st));
         if (c->density_mode == 0)
             HIPCHK(c, soma::launch_fold(c->cw, c->counts(), c->delta(0), c->counts(), c->L.count_words, c->status(), st));
         if (c->density_mode == 2) {
@@ -521,6 +672,7 @@ int record_sweeps(soma_ctx *c, int32_t n, hipStream_t st)
             f.status = c->status();
             HIPCHK(c, soma::launch_fold_faces(c->cw, f, c->L.n_chunks, st));
         }
+        if (ev) HIPCHK(c, hipEventRecord(ev[3 * r + 2], st));
     }
     HIPCHK(c, soma::launch_advance(c->sweep_ctr(), (uint32_t)n, st));
     return SOMA_OK;
@@ -587,6 +739,18 @@ int fetch_chain_ids(soma_ctx *c, const HostSys &h, std::vector<uint32_t> &cid)
     return SOMA_OK;
 }
 
+// Chain classes of one system in logical chain order.
+int fetch_classes(soma_ctx *c, const HostSys &h, std::vector<uint8_t> &cls)
+{
+    cls.resize((size_t)h.d.n_chains);
+    HIPCHK(c, hipMemcpyAsync(cls.data(), c->chain_class() + h.dev.chain_off, cls.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (uint8_t v : cls)
+        if (v > 1) return fail(c, SOMA_EDEVICE, "corrupt chain class table");
+    return SOMA_OK;
+}
+
 // Stored slots of one system in logical chain order (chain L at L * stride).
 int download_slots(soma_ctx *c, const HostSys &h, std::vector<float> (&P)[3], std::vector<int> (&Cv)[3])
 {
@@ -634,6 +798,42 @@ int upload_slots(soma_ctx *c, const HostSys &h, const std::vector<float> (&P)[3]
     return SOMA_OK;
 }
 
+// n sweeps of every system: chain reorders at multiples of reorder_every,
+// then segments replayed from cached graphs (or launched eagerly without
+// graphs, and always when per-kernel events are requested).
+int run_sweeps(soma_ctx *c, int32_t n, hipEvent_t *ev)
+{
+    int rc = SOMA_OK;
+    if (n > 0 && (rc = sweep_layout(c)) != SOMA_OK) return rc;
+    const uint64_t R = (uint64_t)c->opt.reorder_every;
+    int32_t left = n;
+    while (left > 0) {
+        // reorders happen at sweep counts that are multiples of R, however
+        // the sweeps are split over calls
+        if (R > 0 && c->sweep % R == 0 && c->last_reorder != c->sweep)
+            if ((rc = reorder_chains(c)) != SOMA_OK) return rc;
+        int32_t seg = left;
+        if (R > 0) seg = (int32_t)std::min<uint64_t>((uint64_t)left, R - c->sweep % R);
+        if (seg > kGraphChunk) seg = kGraphChunk;
+        if (c->opt.use_graph && !ev) {
+            hipGraphExec_t ex;
+            if ((rc = graph_for(c, seg, &ex)) != SOMA_OK) return rc;
+            HIPCHK(c, hipGraphLaunch(ex, c->stream));
+        } else {
+            if ((rc = record_sweeps(c, seg, c->stream, ev ? ev + 3 * (size_t)(n - left) : nullptr)) != SOMA_OK)
+                return rc;
+        }
+        c->sweep += (uint64_t)seg;
+        c->swept += (uint64_t)seg;
+        left -= seg;
+    }
+    if (n > 0 && c->density_mode == 2) {
+        c->flux_dirty = true;
+        c->flux_sweep = c->sweep;
+    }
+    return SOMA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -666,7 +866,10 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
     c->density_mode = opt->density_mode;
     c->stream = reinterpret_cast<hipStream_t>(opt->hip_stream);
     c->L = plan(sys, n_sys, opt, &c->sys);
-    for (const HostSys &h : c->sys) c->any_smc |= h.dev.smc;
+    for (const HostSys &h : c->sys) {
+        c->any_smc |= h.dev.smc;
+        c->any_zones |= h.dev.zones;
+    }
     if (workspace_bytes < c->L.total) {
         char b[128];
         std::snprintf(b, sizeof b, "workspace has %zu bytes, needs %zu", workspace_bytes, c->L.total);
@@ -715,29 +918,24 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->accept()),
                                              2 * (int64_t)soma::kAcceptSlots * soma::kAcceptStride * n_sys, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(c->status(), 16, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->conv()), 4 * (int64_t)n_sys, 0u, c->stream));
              return (int)SOMA_OK;
          }()) != SOMA_OK)
         return bail(rc);
+    {
+        // chain classes by logical id: [0, n_chains_a) pattern a, the rest b
+        std::vector<uint8_t> cls((size_t)c->L.total_chains);
+        for (const HostSys &h : c->sys)
+            for (int32_t k = 0; k < h.d.n_chains; ++k) cls[(size_t)h.dev.chain_off + k] = k < h.d.n_chains_a ? 0 : 1;
+        if (!cls.empty() &&
+            ((e = hipMemcpyAsync(c->chain_class(), cls.data(), cls.size(), hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+             (e = hipStreamSynchronize(c->stream)) != hipSuccess))
+            return bail(hip_fail(c, e, "upload chain classes"));
+    }
     if ((e = soma::launch_iota_chains(reorder_args(c), c->stream)) != hipSuccess)
         return bail(hip_fail(c, e, "chain ids"));
-    for (const HostSys &h : c->sys) {
-        soma::InitArgs ia{};
-        ia.repr = c->repr;
-        ia.n_chains = h.d.n_chains;
-        ia.N = h.d.N;
-        ia.stride = 2 * h.dev.P;
-        ia.slot_off = h.dev.slot_off;
-        ia.sys_id = h.dev.sys_id;
-        ia.seed = opt->seed;
-        for (int a = 0; a < 3; ++a) {
-            ia.box[a] = h.d.box[a];
-            ia.edge[a] = h.dev.edge[a];
-            (&ia.P0)[a] = c->P(a);
-            (&ia.C0)[a] = c->C(a);
-        }
-        ia.sigma = h.d.Re / std::sqrt(3.0 * (h.d.N - 1));
-        if ((e = soma::launch_init(ia, c->stream)) != hipSuccess) return bail(hip_fail(c, e, "init kernel"));
-    }
+    for (const HostSys &h : c->sys)
+        if ((e = soma::launch_init(init_args(c, h), c->stream)) != hipSuccess) return bail(hip_fail(c, e, "init kernel"));
     if ((rc = rebuild_density(c, -1)) != SOMA_OK) return bail(rc);
     if (opt->reorder_every > 0 && (rc = reorder_chains(c)) != SOMA_OK) return bail(rc);
     if ((rc = sync_status(c)) != SOMA_OK) return bail(rc);
@@ -760,32 +958,37 @@ int soma_mc_sweep(soma_ctx *c, int32_t n)
     int rc = check_ctx(c);
     if (rc != SOMA_OK) return rc;
     if (n < 0) return fail(c, SOMA_EINVAL, "n_sweeps must be >= 0");
-    if (n > 0 && (rc = sweep_layout(c)) != SOMA_OK) return rc;
-    const uint64_t R = (uint64_t)c->opt.reorder_every;
-    int32_t left = n;
-    while (left > 0) {
-        // reorders happen at sweep counts that are multiples of R, however
-        // the sweeps are split over calls
-        if (R > 0 && c->sweep % R == 0 && c->last_reorder != c->sweep)
-            if ((rc = reorder_chains(c)) != SOMA_OK) return rc;
-        int32_t seg = left;
-        if (R > 0) seg = (int32_t)std::min<uint64_t>((uint64_t)left, R - c->sweep % R);
-        if (seg > kGraphChunk) seg = kGraphChunk;
-        if (c->opt.use_graph) {
-            hipGraphExec_t ex;
-            if ((rc = graph_for(c, seg, &ex)) != SOMA_OK) return rc;
-            HIPCHK(c, hipGraphLaunch(ex, c->stream));
-        } else {
-            if ((rc = record_sweeps(c, seg, c->stream)) != SOMA_OK) return rc;
-        }
-        c->sweep += (uint64_t)seg;
-        c->swept += (uint64_t)seg;
-        left -= seg;
+    return run_sweeps(c, n, nullptr);
+}
+
+int soma_time_kernels(soma_ctx *c, int32_t n, soma_ktimes *out)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if (n < 1 || n > 1000) return fail(c, SOMA_EINVAL, "n_sweeps must be in [1, 1000]");
+    if (!out) return fail(c, SOMA_EINVAL, "out is null");
+    std::vector<hipEvent_t> ev(3 * (size_t)n, nullptr);
+    auto release = [&]() { for (hipEvent_t e : ev) if (e) (void)hipEventDestroy(e); };
+    for (hipEvent_t &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) { release(); return fail(c, SOMA_EDEVICE, "hipEventCreate"); }
+    rc = run_sweeps(c, n, ev.data());
+    if (rc == SOMA_OK) rc = sync_status(c);
+    double ks = 0.0, kf = 0.0;
+    for (int32_t r = 0; rc == SOMA_OK && r < n; ++r) {
+        float a = 0.0f, b = 0.0f;
+        if (hipEventElapsedTime(&a, ev[3 * r], ev[3 * r + 1]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[3 * r + 1], ev[3 * r + 2]) != hipSuccess)
+            rc = fail(c, SOMA_EDEVICE, "hipEventElapsedTime");
+        ks += a;
+        if (c->density_mode != 1) kf += b;   // mode 1 launches no fold kernel
     }
-    if (n > 0 && c->density_mode == 2) {
-        c->flux_dirty = true;
-        c->flux_sweep = c->sweep;
-    }
+    release();
+    if (rc != SOMA_OK) return rc;
+    out->n_sweeps = n;
+    out->density_mode = c->density_mode;
+    out->sweep_kernel_us = 1e3 * ks / n;
+    out->fold_kernel_us = 1e3 * kf / n;
+    out->sweep_us = out->sweep_kernel_us + out->fold_kernel_us;
     return SOMA_OK;
 }
 
@@ -825,6 +1028,7 @@ int soma_fields(soma_ctx *c, int32_t sys, float *dst, int32_t dst_on_device)
     f.n_cells = h.dev.n_cells;
     f.counts = c->counts();
     f.omega = c->omega();
+    f.tgt = c->tgt();
     f.out = dst_on_device ? dst : static_cast<float *>(c->staging());
     HIPCHK(c, soma::launch_fields(c->cw, f, c->stream));
     if (!dst_on_device)
@@ -860,12 +1064,16 @@ int soma_observables(soma_ctx *c, int32_t sys, soma_obs *out)
     a.chiN = h.d.chiN;
     a.kappaN = h.d.kappaN;
     a.ham_form = h.d.ham_form;
+    a.umb_lambda = h.dev.umb ? h.umb_lambda : 0.0;
+    a.tgt = c->tgt();
     a.partials = c->partials();
     a.block_base = 0;
     HIPCHK(c, soma::launch_observables(c->cw, a, c->obs_out(), c->stream));
     double q[6];
+    unsigned long long conv[2] = {0, 0};
     std::vector<unsigned long long> slots((size_t)soma::kAcceptSlots * soma::kAcceptStride);
     HIPCHK(c, hipMemcpyAsync(q, c->obs_out(), sizeof q, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(conv, c->conv() + 2 * (size_t)sys, sizeof conv, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(slots.data(), c->accept() + (size_t)sys * slots.size(),
                              sizeof(unsigned long long) * slots.size(), hipMemcpyDeviceToHost, c->stream));
     if ((rc = sync_status(c)) != SOMA_OK) return rc;
@@ -882,6 +1090,8 @@ int soma_observables(soma_ctx *c, int32_t sys, soma_obs *out)
     out->n_moves = (uint64_t)(c->swept * (uint64_t)B);
     out->n_accepted = acc;
     out->accept_ratio = out->n_moves ? (double)acc / (double)out->n_moves : 0.0;
+    out->converted_to_a = conv[0];
+    out->converted_to_b = conv[1];
     return SOMA_OK;
 }
 
@@ -925,6 +1135,15 @@ int soma_set_positions(soma_ctx *c, int32_t sys, const double *xyz)
     std::vector<float> P[3];
     std::vector<int> Cv[3];
     quantise_host(c, h, xyz, P, Cv);
+    if (h.dev.walls) {
+        std::vector<int> zc((size_t)B);
+        for (int64_t ch = 0, j = 0; ch < h.d.n_chains; ++ch)
+            for (int i = 0; i < h.d.N; ++i, ++j) {
+                const size_t sl = (size_t)(ch * 2 * h.dev.P + i);
+                zc[(size_t)j] = c->repr == soma::REPR_CELL ? Cv[2][sl] : z_floor(P[2][sl], h.dev.edge[2]);
+            }
+        if (!inside_walls(h, zc)) return fail(c, SOMA_EINVAL, "positions outside the walls");
+    }
     if ((rc = upload_slots(c, h, P, Cv)) != SOMA_OK) return rc;
     if ((rc = rebuild_density(c, sys)) != SOMA_OK) return rc;
     return sync_status(c);
@@ -980,6 +1199,15 @@ int soma_set_state(soma_ctx *c, int32_t sys, const float *f32, const int32_t *ce
                 P[a][s] = v;
             }
     }
+    if (h.dev.walls) {
+        std::vector<int> zc((size_t)B);
+        for (int64_t ch = 0, j = 0; ch < h.d.n_chains; ++ch)
+            for (int i = 0; i < N; ++i, ++j) {
+                const size_t sl = (size_t)(ch * stride + i);
+                zc[(size_t)j] = c->repr == soma::REPR_CELL ? Cv[2][sl] : z_floor(P[2][sl], h.dev.edge[2]);
+            }
+        if (!inside_walls(h, zc)) return fail(c, SOMA_EINVAL, "state outside the walls");
+    }
     if ((rc = upload_slots(c, h, P, Cv)) != SOMA_OK) return rc;
     if ((rc = rebuild_density(c, sys)) != SOMA_OK) return rc;
     return sync_status(c);
@@ -1011,6 +1239,113 @@ int soma_release_fields(soma_ctx *c, int32_t sys)
     if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
     c->sys[sys].dev.frozen = 0;
     if ((rc = upload_sys(c, sys)) != SOMA_OK) return rc;
+    return sync_status(c);
+}
+
+int soma_place_from_fields(soma_ctx *c, int32_t sys, const float *phi)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!phi) return fail(c, SOMA_EINVAL, "phi_target is null");
+    if (!c->tgt()) return fail(c, SOMA_EINVAL, "the context was created without the coupling workspace (opts.coupling)");
+    HostSys &h = c->sys[sys];
+    const int64_t M = h.dev.n_cells;
+    std::vector<float2> t((size_t)M);
+    for (int64_t i = 0; i < M; ++i) {
+        const float a = phi[i], b = phi[M + i];
+        if (!(a >= 0.0f && a <= 4096.0f && b >= 0.0f && b <= 4096.0f))
+            return fail(c, SOMA_EINVAL, "target fields must be finite and in [0, 4096]");
+        t[(size_t)i] = make_float2(a, b);
+    }
+    // classes with chains need weight somewhere (the integer weights of the kernels)
+    int na_k[2] = {0, 0};
+    for (int k = 0; k < 2; ++k) {
+        const std::vector<uint8_t> &pat = k == 0 ? h.pa : h.pb;
+        int na = 0;
+        for (int i = 0; i < h.d.N; ++i) na += pat[i] == 0;
+        const double fa = (double)na / (double)h.d.N, fb = (double)(h.d.N - na) / (double)h.d.N;
+        bool any = false;
+        for (int64_t i = 0; i < M && !any; ++i)
+            any = std::floor(1048576.0 * (fa * (double)t[(size_t)i].x + fb * (double)t[(size_t)i].y) + 0.5) > 0.0;
+        na_k[k] = na;
+        h.cls_weight[k] = any;
+    }
+    std::vector<uint8_t> cls;
+    if ((rc = fetch_classes(c, h, cls)) != SOMA_OK) return rc;
+    for (uint8_t v : cls)
+        if (!h.cls_weight[v]) return fail(c, SOMA_EINVAL, "a chain class has no target weight anywhere");
+    if ((rc = canonicalize(c)) != SOMA_OK) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->tgt() + h.dev.cell_off, t.data(), sizeof(float2) * (size_t)M, hipMemcpyHostToDevice,
+                             c->stream));
+    soma::PlaceArgs pa{};
+    pa.ia = init_args(c, h);
+    pa.sys = c->d_sys() + sys;
+    pa.chain_id = c->chain_id();
+    pa.chain_class = c->chain_class();
+    pa.chain_off = h.dev.chain_off;
+    pa.cell_off = h.dev.cell_off;
+    pa.n_cells = M;
+    for (int a = 0; a < 3; ++a) {
+        pa.grid[a] = h.d.grid[a];
+        pa.edge64[a] = h.d.box[a] / (double)h.d.grid[a];
+    }
+    pa.Re = h.d.Re;
+    pa.tgt = c->tgt();
+    pa.W = reinterpret_cast<unsigned long long *>(c->ws + c->L.place_W);
+    pa.na[0] = na_k[0];
+    pa.na[1] = na_k[1];
+    HIPCHK(c, soma::launch_place(pa, reinterpret_cast<unsigned long long *>(c->ws + c->L.place_bsum), c->stream));
+    h.has_target = true;
+    if ((rc = rebuild_density(c, sys)) != SOMA_OK) return rc;
+    return sync_status(c);
+}
+
+int soma_set_umbrella(soma_ctx *c, int32_t sys, double lambda)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(c, SOMA_EINVAL, "lambda must be finite and >= 0");
+    HostSys &h = c->sys[sys];
+    if (lambda > 0.0 && !h.has_target) return fail(c, SOMA_EINVAL, "no target fields (soma_place_from_fields first)");
+    const int before = any_coupling(c);
+    h.umb_lambda = lambda;
+    h.dev.umb = lambda > 0.0 ? 1 : 0;
+    set_field_coefs(h);
+    if (any_coupling(c) != before) drop_graphs(c);     // graphs hold the kernel variant
+    if ((rc = upload_sys(c, sys)) != SOMA_OK) return rc;
+    return sync_status(c);
+}
+
+int soma_get_classes(soma_ctx *c, int32_t sys, uint8_t *out)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!out) return fail(c, SOMA_EINVAL, "cls is null");
+    std::vector<uint8_t> cls;
+    if ((rc = fetch_classes(c, c->sys[sys], cls)) != SOMA_OK) return rc;
+    std::memcpy(out, cls.data(), cls.size());
+    return sync_status(c);
+}
+
+int soma_set_classes(soma_ctx *c, int32_t sys, const uint8_t *in)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!in) return fail(c, SOMA_EINVAL, "cls is null");
+    HostSys &h = c->sys[sys];
+    for (int32_t k = 0; k < h.d.n_chains; ++k)
+        if (in[k] > 1) return fail(c, SOMA_EINVAL, "classes must be 0 or 1");
+    HIPCHK(c, hipMemcpyAsync(c->chain_class() + h.dev.chain_off, in, (size_t)h.d.n_chains, hipMemcpyHostToDevice,
+                             c->stream));
+    const int before = any_coupling(c);
+    h.dev.cls_array = 1;
+    if (any_coupling(c) != before) drop_graphs(c);     // graphs hold the kernel variant
+    if ((rc = upload_sys(c, sys)) != SOMA_OK) return rc;
+    if ((rc = rebuild_density(c, sys)) != SOMA_OK) return rc;
     return sync_status(c);
 }
 
@@ -1052,11 +1387,38 @@ int soma_get_info(soma_ctx *c, soma_info *out)
     return SOMA_OK;
 }
 
+void soma_tune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
+}
+
 int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
 {
     int rc = check_ctx(c);
     if (rc != SOMA_OK) return rc;
     if (trial_sweeps < 1 || trial_sweeps > 1000) return fail(c, SOMA_EINVAL, "trial_sweeps must be in [1, 1000]");
+    const std::string key = tune_key(c);
+    {
+        soma_tune hit{};
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) { hit = it->second; found = true; }
+        }
+        if (found) {
+            // leave the rotation of density mode 1 before switching modes
+            if ((rc = canonicalize(c)) != SOMA_OK) return rc;
+            set_shape(c, hit.waves_per_block, hit.waves_per_cu, hit.xcd_remap);
+            c->density_mode = hit.density_mode;
+            drop_graphs(c);
+            hit.n_candidates = 0;
+            hit.from_cache = 1;
+            if (out) *out = hit;
+            return sync_status(c);
+        }
+    }
     const int n_sys = (int)c->sys.size();
     const size_t pos_bytes = sizeof(float) * (size_t)c->L.total_slots;
     const size_t acc_words = 2 * (size_t)soma::kAcceptSlots * soma::kAcceptStride * n_sys;
@@ -1074,6 +1436,12 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
     HIPCHK(c, hipMemcpyAsync(acc.data(), c->accept(), acc_words * 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(status.data(), c->status(), 16 * 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&ctr, c->sweep_ctr(), sizeof ctr, hipMemcpyDeviceToHost, c->stream));
+    // conversion zones change chain classes and their counters
+    std::vector<unsigned long long> conv(2 * (size_t)n_sys);
+    HIPCHK(c, hipMemcpyAsync(conv.data(), c->conv(), sizeof(unsigned long long) * conv.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->chain_class2(), c->chain_class(), (size_t)c->L.total_chains, hipMemcpyDeviceToDevice,
+                             c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
 
     // Every candidate starts from the saved state and runs the same sweeps
@@ -1091,6 +1459,8 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
                 HIPCHK(c, hipMemcpyAsync(c->C(d), c->D(d), pos_bytes, hipMemcpyDeviceToDevice, c->stream));
         }
         HIPCHK(c, hipMemcpyAsync(c->sweep_ctr(), &ctr, sizeof ctr, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->chain_class(), c->chain_class2(), (size_t)c->L.total_chains,
+                                 hipMemcpyDeviceToDevice, c->stream));
         return rebuild_density(c, -1);
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1127,7 +1497,7 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
         us = 1e3 * (double)ms / trial_sweeps;
         return SOMA_OK;
     };
-    soma_tune best{c->waves_per_block, c->waves_per_cu, c->xcd_remap, c->density_mode, 0, 0.0, 0.0};
+    soma_tune best{c->waves_per_block, c->waves_per_cu, c->xcd_remap, c->density_mode, 0, 0.0, 0.0, 0};
     rc = time_shape(best.waves_per_block, best.waves_per_cu, best.xcd_remap, best.density_mode,
                     best.us_per_sweep_before);
     best.us_per_sweep = best.us_per_sweep_before;
@@ -1137,6 +1507,7 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
             for (int wpcu : kWpcu)
                 for (int xcd : kXcd) {
                     if (rc != SOMA_OK) break;
+                    if (dm == 2 && c->any_zones) continue;   // conversions need cell words
                     double us = 0.0;
                     rc = time_shape(wpb, wpcu, xcd, dm, us);
                     ++best.n_candidates;
@@ -1159,8 +1530,15 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
     if ((rc = restore()) != SOMA_OK) return rc;
     HIPCHK(c, hipMemcpyAsync(c->accept(), acc.data(), acc_words * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->status(), status.data(), 16 * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->conv(), conv.data(), sizeof(unsigned long long) * conv.size(), hipMemcpyHostToDevice,
+                             c->stream));
     if (out) *out = best;
-    return sync_status(c);
+    rc = sync_status(c);
+    if (rc == SOMA_OK) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    return rc;
 }
 
 const char *soma_last_error(const soma_ctx *c)

@@ -486,11 +486,11 @@ __device__ __forceinline__ float omega_at(bool frozen, const float2 *omega, cons
 // as values and selected by value: a per-lane choice between word addresses
 // compiled (gfx950, -O3) into divergent branches that left the address of
 // the fourth word unset for beads 96..127.
-__device__ __forceinline__ int pattern_type(const DevSys &S, int chain, int i)
+__device__ __forceinline__ int pattern_type(const DevSys &S, int cls, int i)
 {
     const uint4 pa = *reinterpret_cast<const uint4 *>(S.pat_a);
     const uint4 pb = *reinterpret_cast<const uint4 *>(S.pat_b);
-    const bool use_a = chain < S.n_chains_a;
+    const bool use_a = cls == 0;
     const uint32_t x = use_a ? pa.x : pb.x, y = use_a ? pa.y : pb.y;
     const uint32_t z = use_a ? pa.z : pb.z, w = use_a ? pa.w : pb.w;
     const int k = i >> 5;
@@ -498,6 +498,22 @@ __device__ __forceinline__ int pattern_type(const DevSys &S, int chain, int i)
     const uint32_t word = (k & 2) ? hi : lo;
     return (int)((word >> (i & 31)) & 1u);
 }
+
+// Class of a chain (which pattern it carries): from the class array when
+// conversion zones (or the caller) change classes, else chains
+// [0, n_chains_a) are class a.
+template <bool CPL = true>
+__device__ __forceinline__ int chain_cls(const DevSys &S, const uint8_t *cc, uint32_t clog)
+{
+    if constexpr (CPL)
+        if (S.cls_array) return (int)cc[S.chain_off + clog];
+    return (int)clog < S.n_chains_a ? 0 : 1;
+}
+
+// Unwrapped z cell of a bead: the floor computed by locate/step for FP32
+// positions, the stored cell for cell + offset positions.
+__device__ __forceinline__ int zcell(const CellPos &c, const BeadF32 &) { return (int)c.fz; }
+__device__ __forceinline__ int zcell(const CellPos &, const BeadCell &b) { return b.cz; }
 
 __device__ __forceinline__ int wave_tile(int waves_per_block, int xcd_remap)
 {
@@ -593,28 +609,30 @@ __device__ __forceinline__ void emit_faces(uint32_t *keys, uint32_t *vals, int64
     }
 }
 
-// End of a wave tile: the density delta of the beads that changed cell --
-// cell words (density modes 0, 1) or face fluxes (mode 2) -- merged per wave
-// in LDS, then one device atomic per distinct word with a nonzero sum; the
-// acceptance count and the cell-range status.
+// End of a wave tile: the density delta of the beads whose (cell, type)
+// changed -- cell words (density modes 0, 1) or face fluxes (mode 2) --
+// merged per wave in LDS, then one device atomic per distinct word with a
+// nonzero sum; the acceptance count and the cell-range status.  Bead j moved
+// from cell o_j with type t_j to cell f_j with type u_j (u_j != t_j only
+// for a chain converted in a boundary zone, never in mode 2); m_j says that
+// something changed.
 template <int CW, int DM>
 __device__ __forceinline__ void tile_finish(const SweepArgs &a, int wave, uint32_t sys, int64_t cell_off,
                                             const SysView &v, uint32_t *dcur, uint32_t *agg_keys,
-                                            uint32_t *agg_vals, bool m0, const CellPos &o0, const CellPos &n0,
-                                            int t0, bool m1, const CellPos &o1, const CellPos &n1, int t1,
-                                            bool acc0, bool acc1, bool bad)
+                                            uint32_t *agg_vals, bool m0, const CellPos &o0, const CellPos &f0,
+                                            int t0, int u0, bool m1, const CellPos &o1, const CellPos &f1, int t1,
+                                            int u1, bool acc0, bool acc1, bool bad)
 {
     constexpr int SLOTS = DM == 2 ? kAggSlotsFaces : kAggSlotsCells;
     const int lane = (int)(threadIdx.x & 63);
     if constexpr (DM == 2) {
-        emit_faces<CW>(agg_keys, agg_vals, a.count_words, cell_off, o0, n0, t0, m0, v);
-        emit_faces<CW>(agg_keys, agg_vals, a.count_words, cell_off, o1, n1, t1, m1, v);
+        emit_faces<CW>(agg_keys, agg_vals, a.count_words, cell_off, o0, f0, t0, m0, v);
+        emit_faces<CW>(agg_keys, agg_vals, a.count_words, cell_off, o1, f1, t1, m1, v);
     } else {
-        const uint32_t i0 = count_inc<CW>(t0), i1 = count_inc<CW>(t1);
-        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(o0, v), t0) + 1u, 0u - i0, m0);
-        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(n0, v), t0) + 1u, i0, m0);
-        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(o1, v), t1) + 1u, 0u - i1, m1);
-        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(n1, v), t1) + 1u, i1, m1);
+        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(o0, v), t0) + 1u, 0u - count_inc<CW>(t0), m0);
+        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(f0, v), u0) + 1u, count_inc<CW>(u0), m0);
+        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(o1, v), t1) + 1u, 0u - count_inc<CW>(t1), m1);
+        agg_insert<SLOTS>(agg_keys, agg_vals, count_word<CW>(cell_off + lin(f1, v), u1) + 1u, count_inc<CW>(u1), m1);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     for (int k = lane; k < SLOTS; k += 64) {
@@ -633,7 +651,51 @@ __device__ __forceinline__ void tile_finish(const SweepArgs &a, int wave, uint32
     }
 }
 
-template <int R, int CW, int DM, class Bead>
+// Boundary-zone conversion (Sec. 3.2, "Coupling"), after the moves of a
+// sweep: a chain whose binned centre -- the mean of its beads' z-cell
+// indexes, compared as the exact integer sum -- lies in the lower zone
+// becomes class a, in the upper zone class b.  zf0, zf1: the final z cells of
+// this lane's beads.  Returns the chain's new class; the chain's first lane
+// stores it and the wave counts the conversions.
+__device__ __forceinline__ int zone_convert(const SweepArgs &a, const DevSys &S, uint32_t sys, uint32_t clog,
+                                            int cls, bool active, int p, int P, bool has1, int zf0, int zf1)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    int z = active ? zf0 + (has1 ? zf1 : 0) : 0;
+    // segmented sum over the chain's P lanes: lane p ends with the sum over
+    // [p, P) of its chain, so the chain's first lane holds the total
+    for (int o = 1; o < 64; o <<= 1) {
+        const int w = __shfl_down(z, o);
+        if (p + o < P) z += w;
+    }
+    const int sum = __shfl(z, lane - p);
+    int nc = cls;
+    if (S.zone_a && sum < S.zone_a_lim) nc = 0;
+    else if (S.zone_b && sum >= S.zone_b_lim) nc = 1;
+    const bool conv = active && p == 0 && nc != cls;
+    if (conv) a.chain_class[S.chain_off + clog] = (uint8_t)nc;
+    const uint64_t to_a = __popcll(__ballot(conv && nc == 0)), to_b = __popcll(__ballot(conv && nc == 1));
+    if (lane == 0) {
+        if (to_a) atomicAdd(a.conv + 2 * sys, (unsigned long long)to_a);
+        if (to_b) atomicAdd(a.conv + 2 * sys + 1, (unsigned long long)to_b);
+    }
+    return active ? nc : cls;
+}
+
+// Trial position outside the walls (z cell outside [wall_lo, wall_hi)).
+__device__ __forceinline__ bool outside_walls(const DevSys &S, int zc)
+{
+    return S.walls && (zc < S.wall_lo || zc >= S.wall_hi);
+}
+
+// Umbrella part of the field difference of a bead of type t between its
+// trial and its old cell: -lambda/N (target_t(new) - target_t(old)).
+__device__ __forceinline__ float umb_step(float coef, float2 tn, float2 to, int t)
+{
+    return coef * (t ? to.y - tn.y : to.x - tn.x);
+}
+
+template <int R, int CW, int DM, bool CPL, class Bead>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                            const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
                                            uint32_t *agg_vals, Bead b0, Bead b1)
@@ -663,8 +725,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     // logical chain id: keys the random numbers and picks the species, so
     // results do not depend on where a chain sits in memory
     const uint32_t clog = a.chain_id[S.chain_off + chain];
-    const int t0 = pattern_type(S, (int)clog, i0);
-    const int t1 = pattern_type(S, (int)clog, i1 < N ? i1 : i0);
+    const int cls = chain_cls<CPL>(S, a.chain_class, clog);
+    const int t0 = pattern_type(S, cls, i0);
+    const int t1 = pattern_type(S, cls, i1 < N ? i1 : i0);
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const float delta_s = S.delta * 0x1p-23f;
     const Draw d0 = move_draw((uint32_t)i0, clog, (uint32_t)s, S.sys_id, k0, k1, delta_s);
@@ -683,7 +746,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     const CellPos s0 = step(c0, b0, n0, v), s1 = step(c1, b1, n1, v);
     const int nc0 = lin(s0, v);
     const int nc1 = lin(s1, v);
-    const bool g0 = active && nc0 != old0, g1 = has1 && nc1 != old1;
+    // walls: a trial position outside the slab is rejected (and needs no field)
+    const bool out0 = CPL && outside_walls(S, zcell(s0, n0)), out1 = CPL && outside_walls(S, zcell(s1, n1));
+    const bool g0 = active && nc0 != old0 && !out0, g1 = has1 && nc1 != old1 && !out1;
     float dw0 = 0.0f, dw1 = 0.0f;
     if (frozen) {
         float2 wn0{0.f, 0.f}, wo0{0.f, 0.f}, wn1{0.f, 0.f}, wo1{0.f, 0.f};
@@ -701,8 +766,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
             rn1 = load_raw<CW, DM == 1>(cin, dprev, cell_off + nc1);
             ro1 = load_raw<CW, DM == 1>(cin, dprev, cell_off + old1);
         }
+        float2 un0{0.f, 0.f}, uo0{0.f, 0.f}, un1{0.f, 0.f}, uo1{0.f, 0.f};
+        const bool umb = CPL && S.umb != 0;
+        if (umb) {
+            if (g0) { un0 = a.tgt[cell_off + nc0]; uo0 = a.tgt[cell_off + old0]; }
+            if (g1) { un1 = a.tgt[cell_off + nc1]; uo1 = a.tgt[cell_off + old1]; }
+        }
         if (g0) dw0 = omega_of(fc, counts_of<CW>(rn0), t0) - omega_of(fc, counts_of<CW>(ro0), t0);
         if (g1) dw1 = omega_of(fc, counts_of<CW>(rn1), t1) - omega_of(fc, counts_of<CW>(ro1), t1);
+        if (umb) {
+            dw0 += umb_step(S.umb_coef, un0, uo0, t0);
+            dw1 += umb_step(S.umb_coef, un1, uo1, t1);
+        }
     }
     const float kh = S.k_half;
 
@@ -716,7 +791,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
         if (p > 0) dE += 2.0f * dot3(de, bond(b0, left, v)) + dd;
         if (i1 < N) dE += 2.0f * dot3(de, bond(b0, b1, v)) + dd;
         dE = dE * kh + dw0;
-        acc0 = active && (d0.u < __expf(-dE));
+        acc0 = active && !out0 && (d0.u < __expf(-dE));
         if (acc0) b0 = n0;
     }
     // odd pass: bead 2p+1, neighbours 2p (this lane, updated) and 2p+2 (next lane)
@@ -728,12 +803,22 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
         float dE = 2.0f * dot3(de, bond(b1, b0, v)) + dd;
         if (i1 + 1 < N) dE += 2.0f * dot3(de, bond(b1, right, v)) + dd;
         dE = dE * kh + dw1;
-        acc1 = has1 && (d1.u < __expf(-dE));
+        acc1 = has1 && !out1 && (d1.u < __expf(-dE));
         if (acc1) b1 = n1;
     }
     if (active) store_pair(A, slot, b0, b1);
-    tile_finish<CW, DM>(a, wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals, acc0 && nc0 != old0, c0, s0, t0,
-                        acc1 && nc1 != old1, c1, s1, t1, acc0, acc1, active && bad);
+    // final cells: without coupling a change implies an accepted move, so the
+    // trial cells serve (and the selection costs no registers)
+    const CellPos f0 = CPL ? (acc0 ? s0 : c0) : s0, f1 = CPL ? (acc1 ? s1 : c1) : s1;
+    int u0 = t0, u1 = t1;
+    if (CPL && S.zones) {
+        const int ncls = zone_convert(a, S, T.sys, clog, cls, active, p, P, has1, zcell(f0, b0), zcell(f1, b1));
+        u0 = pattern_type(S, ncls, i0);
+        u1 = pattern_type(S, ncls, i1 < N ? i1 : i0);
+    }
+    tile_finish<CW, DM>(a, wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals,
+                        active && ((acc0 && nc0 != old0) || u0 != t0), c0, f0, t0, u0,
+                        has1 && ((acc1 && nc1 != old1) || u1 != t1), c1, f1, t1, u1, acc0, acc1, active && bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -819,7 +904,7 @@ __device__ __forceinline__ float smc_log_ratio(const DevSys &S, float3 de, doubl
 template <int CW, int DM>
 __device__ __forceinline__ float field_step(const SweepArgs &a, bool frozen, const FieldCoef &fc,
                                             const uint32_t *cin, const uint32_t *dprev, int64_t cell_off,
-                                            int nc, int old, int t, bool gather)
+                                            int nc, int old, int t, bool gather, bool umb, float umb_coef)
 {
     float dw = 0.0f;
     if (frozen) {
@@ -831,7 +916,10 @@ __device__ __forceinline__ float field_step(const SweepArgs &a, bool frozen, con
         if (gather) {
             rn = load_raw<CW, DM == 1>(cin, dprev, cell_off + nc);
             ro = load_raw<CW, DM == 1>(cin, dprev, cell_off + old);
+            float2 un{0.f, 0.f}, uo{0.f, 0.f};
+            if (umb) { un = a.tgt[cell_off + nc]; uo = a.tgt[cell_off + old]; }
             dw = omega_of(fc, counts_of<CW>(rn), t) - omega_of(fc, counts_of<CW>(ro), t);
+            if (umb) dw += umb_step(umb_coef, un, uo, t);
         }
     }
     return dw;
@@ -840,7 +928,7 @@ __device__ __forceinline__ float field_step(const SweepArgs &a, bool frozen, con
 // One wave tile with smart moves.  The odd bead's proposal depends on the
 // even pass (its bond force uses the moved even beads), so the two passes
 // gather their fields one after the other.
-template <int R, int CW, int DM, class Bead>
+template <int R, int CW, int DM, bool CPL, class Bead>
 __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                                const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
                                                uint32_t *agg_vals, Bead b0, Bead b1)
@@ -863,10 +951,13 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
     const int64_t slot = S.slot_off + (int64_t)chain * (2 * P) + i0;
     const PosArrays A{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2};
     const uint32_t clog = a.chain_id[S.chain_off + chain];
-    const int t0 = pattern_type(S, (int)clog, i0);
-    const int t1 = pattern_type(S, (int)clog, i1 < N ? i1 : i0);
+    const int cls = chain_cls<CPL>(S, a.chain_class, clog);
+    const int t0 = pattern_type(S, cls, i0);
+    const int t1 = pattern_type(S, cls, i1 < N ? i1 : i0);
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const float kh = S.k_half;
+    const bool umb = CPL && S.umb != 0;
+    const float umb_coef = S.umb_coef;
     bool bad = false;
     const CellPos c0 = locate(b0, v, bad);
     const CellPos c1 = locate(b1, v, bad);
@@ -888,8 +979,9 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
         const Bead n0 = smc_propose(b0, left, hl, b1, hr, S, v, xi, F, inside);
         s0 = step(c0, b0, n0, v);
         nc0 = lin(s0, v);
+        if (CPL) inside = inside && !outside_walls(S, zcell(s0, n0));
         const float dw = field_step<CW, DM>(a, frozen, fc, cin, dprev, cell_off, nc0, old0, t0,
-                                            active && inside && nc0 != old0);
+                                            active && inside && nc0 != old0, umb, umb_coef);
         const float3 de = bond(n0, b0, v);
         const float dd = dot3(de, de);
         float dE = 0.0f;
@@ -914,8 +1006,9 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
         const Bead n1 = smc_propose(b1, b0, true, right, hr, S, v, xi, F, inside);
         s1 = step(c1, b1, n1, v);
         nc1 = lin(s1, v);
+        if (CPL) inside = inside && !outside_walls(S, zcell(s1, n1));
         const float dw = field_step<CW, DM>(a, frozen, fc, cin, dprev, cell_off, nc1, old1, t1,
-                                            has1 && inside && nc1 != old1);
+                                            has1 && inside && nc1 != old1, umb, umb_coef);
         const float3 de = bond(n1, b1, v);
         const float dd = dot3(de, de);
         float dE = 2.0f * dot3(de, bond(b1, b0, v)) + dd;
@@ -925,8 +1018,18 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
         if (acc1) b1 = n1;
     }
     if (active) store_pair(A, slot, b0, b1);
-    tile_finish<CW, DM>(a, wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals, acc0 && nc0 != old0, c0, s0, t0,
-                        acc1 && nc1 != old1, c1, s1, t1, acc0, acc1, active && bad);
+    // final cells: without coupling a change implies an accepted move, so the
+    // trial cells serve (and the selection costs no registers)
+    const CellPos f0 = CPL ? (acc0 ? s0 : c0) : s0, f1 = CPL ? (acc1 ? s1 : c1) : s1;
+    int u0 = t0, u1 = t1;
+    if (CPL && S.zones) {
+        const int ncls = zone_convert(a, S, T.sys, clog, cls, active, p, P, has1, zcell(f0, b0), zcell(f1, b1));
+        u0 = pattern_type(S, ncls, i0);
+        u1 = pattern_type(S, ncls, i1 < N ? i1 : i0);
+    }
+    tile_finish<CW, DM>(a, wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals,
+                        active && ((acc0 && nc0 != old0) || u0 != t0), c0, f0, t0, u0,
+                        has1 && ((acc1 && nc1 != old1) || u1 != t1), c1, f1, t1, u1, acc0, acc1, active && bad);
 }
 
 // The sweep kernel: one launch per sweep for every system.  Wave w of the
@@ -937,7 +1040,7 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
 // one-tile case.  With FI every thread also folds count words of the
 // previous sweep: the first word's loads are issued before the move work
 // and its stores after it, so they overlap.
-template <int R, int CW, bool LOOP, int DM, bool SMC>
+template <int R, int CW, bool LOOP, int DM, bool SMC, bool CPL>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
@@ -973,9 +1076,9 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
             tile_load(a, t, b0, b1);
             agg_clear<SLOTS>(agg_keys, agg_vals);
             if (SMC && a.systems[a.tiles[t].sys].smc)
-                sweep_tile_smc<R, CW, DM>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile_smc<R, CW, DM, CPL>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
             else
-                sweep_tile<R, CW, DM>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile<R, CW, DM, CPL>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
         }
     } else {
         if (wave < a.n_tiles) {
@@ -983,9 +1086,9 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
             tile_load(a, wave, b0, b1);
             agg_clear<SLOTS>(agg_keys, agg_vals);
             if (SMC && a.systems[a.tiles[wave].sys].smc)
-                sweep_tile_smc<R, CW, DM>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile_smc<R, CW, DM, CPL>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
             else
-                sweep_tile<R, CW, DM>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile<R, CW, DM, CPL>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
         }
     }
     if constexpr (FI) {
@@ -1119,11 +1222,11 @@ __global__ __launch_bounds__(256) void k_density(DensityArgs a)
     load_pair(A, slot, b0, b1);
     bool bad = false, ovf = false;
     const int c0 = cell_of(b0, v, bad);
-    const int clog = (int)a.chain_id[S.chain_off + chain];
-    ovf |= scatter_count<CW>(a.counts, S.cell_off + c0, pattern_type(S, clog, i0));
+    const int cls = chain_cls(S, a.chain_class, a.chain_id[S.chain_off + chain]);
+    ovf |= scatter_count<CW>(a.counts, S.cell_off + c0, pattern_type(S, cls, i0));
     if (i1 < N) {
         const int c1 = cell_of(b1, v, bad);
-        ovf |= scatter_count<CW>(a.counts, S.cell_off + c1, pattern_type(S, clog, i1));
+        ovf |= scatter_count<CW>(a.counts, S.cell_off + c1, pattern_type(S, cls, i1));
     }
     if (ovf) atomicOr(a.status, ST_COUNT_OVERFLOW);
     if (bad) atomicOr(a.status, ST_CELL_OVERFLOW);
@@ -1147,6 +1250,11 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs a)
         const uint2 n = load_counts<CW>(a.counts, S.cell_off + c);
         wa = omega_of(fc, n, 0);
         wb = omega_of(fc, n, 1);
+        if (S.umb) {
+            const float2 t = a.tgt[S.cell_off + c];
+            wa -= S.umb_coef * t.x;
+            wb -= S.umb_coef * t.y;
+        }
     }
     a.out[c] = wa;
     a.out[a.n_cells + c] = wb;
@@ -1347,34 +1455,246 @@ __device__ __forceinline__ void store_init(const InitArgs &a, int64_t slot, doub
     }
 }
 
+// Initial streams: counter word 3 = system id with the top bit set (never a
+// move draw); word 2 names the stream and the attempt j (walls only):
+// 4j initial walks, 4j + 1 placement targets, 4j + 2 placement walks.
+__device__ __forceinline__ uint4 init_block(uint32_t w0, uint32_t chain, uint32_t stream, uint32_t sys_id,
+                                            uint64_t seed)
+{
+    return philox4x32_10(make_uint4(w0, chain, stream, sys_id | 0x80000000u), (uint32_t)seed,
+                         (uint32_t)(seed >> 32));
+}
+
+__device__ __forceinline__ double top24(uint32_t w) { return (double)(w >> 8) * 0x1p-24; }
+
+// One Gaussian bond, each component N(0, sigma^2), Box-Muller on words (0,1), (2,3).
+__device__ __forceinline__ double3 gauss_bond(uint4 w, double sigma)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    const double u1 = ((double)(w.x >> 8) + 0.5) * 0x1p-24;
+    const double u2 = top24(w.y);
+    const double u3 = ((double)(w.z >> 8) + 0.5) * 0x1p-24;
+    const double u4 = top24(w.w);
+    const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
+    return make_double3(sigma * r1 * cos(two_pi * u2), sigma * r1 * sin(two_pi * u2), sigma * r2 * cos(two_pi * u4));
+}
+
+// Walls: the z range a drawn chain must stay in, with a margin of 1/128 cell
+// edge so that the stored representation's z cell is inside whatever the
+// rounding (|z| < 2^15 edges).
+__device__ __forceinline__ void wall_range(const InitArgs &a, double &lo, double &hi)
+{
+    const double e = (double)a.edge[2];
+    lo = (double)a.wall_lo * e + e / 128.0;
+    hi = (double)a.wall_hi * e - e / 128.0;
+}
+
+// Bead 0 uniform in the box (in z between the walls when there are walls),
+// bonds Gaussian; with walls a chain that leaves the slab is drawn again
+// from the next attempt's counters (kMaxAttempts at most, else the status
+// bit).  One thread per chain, FP64 along the chain, then rounding to the
+// representation (the last attempt's chain is the one stored).
 __global__ __launch_bounds__(256) void k_init_walks(InitArgs a)
 {
     const int chain = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (chain >= a.n_chains) return;
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const double two_pi = 6.283185307179586476925286766559;
-    double x = 0, y = 0, z = 0;
     const int64_t base = a.slot_off + (int64_t)chain * a.stride;
-    for (int i = 0; i < a.N; ++i) {
-        const uint4 w = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)chain, 0u, a.sys_id | 0x80000000u),
-                                      k0, k1);
-        if (i == 0) {
-            x = a.box[0] * ((double)(w.x >> 8) * 0x1p-24);
-            y = a.box[1] * ((double)(w.y >> 8) * 0x1p-24);
-            z = a.box[2] * ((double)(w.z >> 8) * 0x1p-24);
-        } else {
-            const double u1 = ((double)(w.x >> 8) + 0.5) * 0x1p-24;
-            const double u2 = (double)(w.y >> 8) * 0x1p-24;
-            const double u3 = ((double)(w.z >> 8) + 0.5) * 0x1p-24;
-            const double u4 = (double)(w.w >> 8) * 0x1p-24;
-            const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
-            x += a.sigma * r1 * cos(two_pi * u2);
-            y += a.sigma * r1 * sin(two_pi * u2);
-            z += a.sigma * r2 * cos(two_pi * u4);
+    double zlo = 0.0, zhi = 0.0;
+    if (a.walls) wall_range(a, zlo, zhi);
+    bool ok = false;
+    for (int j = 0; j < kMaxAttempts && !ok; ++j) {
+        ok = true;
+        double x = 0, y = 0, z = 0;
+        for (int i = 0; i < a.N; ++i) {
+            const uint4 w = init_block((uint32_t)i, (uint32_t)chain, 4u * (uint32_t)j, a.sys_id, a.seed);
+            if (i == 0) {
+                x = a.box[0] * top24(w.x);
+                y = a.box[1] * top24(w.y);
+                z = a.box[2] * top24(w.z);
+                if (a.walls) {
+                    const double e = (double)a.edge[2];
+                    const double lo = (double)a.wall_lo * e, hi = (double)a.wall_hi * e;
+                    z = lo + (hi - lo) * top24(w.z);
+                }
+            } else {
+                const double3 b = gauss_bond(w, a.sigma);
+                x += b.x;
+                y += b.y;
+                z += b.z;
+            }
+            if (a.walls && !(z >= zlo && z <= zhi)) ok = false;
+            store_init(a, base + i, x, y, z);
         }
-        store_init(a, base + i, x, y, z);
+        if (!a.walls) break;
     }
+    if (!ok) atomicOr(a.status, ST_PLACEMENT);
     for (int i = a.N; i < a.stride; ++i) store_init(a, base + i, 0.0, 0.0, 0.0);   // padding slot
+}
+
+// ---------------------------------------------------------------------------
+// Placement from target concentration fields (Sec. 3.2, "Coupling"): each
+// molecule is placed within half a mean end-to-end distance of a target
+// position that follows the supplied fields.
+//   1. Class k (pattern a or b, A fraction f_k) weighs cell c by the integer
+//      w_k(c) = floor(2^20 (f_k tA(c) + (1 - f_k) tB(c)) + 1/2) (FP64, exact
+//      as the same operations on any IEEE machine); W_k is its exact
+//      inclusive prefix sum (uint64).
+//   2. A chain of class k takes t = floor(v T_k / 2^64) for the 64-bit word
+//      v of its block (0, chain, 4j + 1) and the first cell with W_k > t.
+//   3. Target point uniform in that cell; centre of mass uniform in the ball
+//      of radius Re/2 around it; conformation a Gaussian walk (blocks
+//      (i, chain, 4j + 2)) shifted to that centre.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_place_weights(PlaceArgs a)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_cells) return;
+    const int N = a.ia.N;
+    const float2 t = a.tgt[a.cell_off + c];
+    for (int k = 0; k < 2; ++k) {
+        const double fa = (double)a.na[k] / (double)N, fb = (double)(N - a.na[k]) / (double)N;
+        const double v = fa * (double)t.x + fb * (double)t.y;
+        a.W[k * a.n_cells + c] = (unsigned long long)floor(1048576.0 * v + 0.5);
+    }
+}
+
+// Inclusive scan of 64-bit words in place (block sums, a one-block scan of
+// the sums, then block-local scans plus offsets), as for the reorder.
+constexpr int kScan64Block = 256, kScan64Per = 8, kScan64Tile = kScan64Block * kScan64Per;
+
+__device__ __forceinline__ unsigned long long block_scan64(unsigned long long v, unsigned long long *sh,
+                                                           unsigned long long &total)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScan64Block; off <<= 1) {
+        const unsigned long long x = t >= off ? sh[t - off] : 0ull;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    total = sh[kScan64Block - 1];
+    const unsigned long long incl = sh[t];
+    __syncthreads();
+    return incl - v;          // exclusive
+}
+
+__global__ __launch_bounds__(kScan64Block) void k_scan64_partials(const unsigned long long *x, int64_t n,
+                                                                  unsigned long long *bsum)
+{
+    __shared__ unsigned long long sh[kScan64Block];
+    const int64_t base = (int64_t)blockIdx.x * kScan64Tile + (int64_t)threadIdx.x * kScan64Per;
+    unsigned long long v = 0;
+    for (int k = 0; k < kScan64Per; ++k)
+        if (base + k < n) v += x[base + k];
+    unsigned long long total;
+    (void)block_scan64(v, sh, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScan64Block) void k_scan64_bsum(unsigned long long *bsum, int nb)
+{
+    __shared__ unsigned long long sh[kScan64Block];
+    unsigned long long carry = 0;
+    for (int start = 0; start < nb; start += kScan64Block) {
+        const int i = start + (int)threadIdx.x;
+        const unsigned long long v = i < nb ? bsum[i] : 0ull;
+        unsigned long long total;
+        const unsigned long long ex = block_scan64(v, sh, total);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kScan64Block) void k_scan64_apply(unsigned long long *x, int64_t n,
+                                                               const unsigned long long *bsum)
+{
+    __shared__ unsigned long long sh[kScan64Block];
+    const int64_t base = (int64_t)blockIdx.x * kScan64Tile + (int64_t)threadIdx.x * kScan64Per;
+    unsigned long long vals[kScan64Per];
+    unsigned long long v = 0;
+    for (int k = 0; k < kScan64Per; ++k) {
+        vals[k] = base + k < n ? x[base + k] : 0ull;
+        v += vals[k];
+    }
+    unsigned long long total;
+    unsigned long long run = bsum[blockIdx.x] + block_scan64(v, sh, total);
+    for (int k = 0; k < kScan64Per; ++k)
+        if (base + k < n) {
+            run += vals[k];
+            x[base + k] = run;      // inclusive
+        }
+}
+
+// One thread per chain slot of the system: the chain with that slot's
+// logical id is placed into it.
+__global__ __launch_bounds__(256) void k_place_chains(PlaceArgs a)
+{
+    const int slot_chain = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const InitArgs &ia = a.ia;
+    if (slot_chain >= ia.n_chains) return;
+    const uint32_t chain = a.chain_id[a.chain_off + slot_chain];
+    const int k = (int)a.chain_class[a.chain_off + chain];
+    const unsigned long long *Wk = a.W + k * a.n_cells;
+    const unsigned long long T = Wk[a.n_cells - 1];
+    const int64_t base = ia.slot_off + (int64_t)slot_chain * ia.stride;
+    const int N = ia.N;
+    const double two_pi = 6.283185307179586476925286766559;
+    double zlo = 0.0, zhi = 0.0;
+    if (ia.walls) wall_range(ia, zlo, zhi);
+    bool ok = false;
+    for (int j = 0; j < kMaxAttempts && !ok && T > 0; ++j) {
+        const uint4 w = init_block(0u, chain, 4u * (uint32_t)j + 1u, ia.sys_id, ia.seed);
+        const uint4 q = init_block(1u, chain, 4u * (uint32_t)j + 1u, ia.sys_id, ia.seed);
+        const unsigned long long v = ((unsigned long long)w.x << 32) | w.y;
+        const unsigned long long t = __umul64hi(v, T);
+        int64_t lo = 0, hi = a.n_cells - 1;     // first cell with Wk > t
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (Wk[mid] > t) hi = mid;
+            else lo = mid + 1;
+        }
+        const int64_t nyz = (int64_t)a.grid[1] * a.grid[2];
+        const int64_t ix = lo / nyz, iy = (lo / a.grid[2]) % a.grid[1], iz = lo % a.grid[2];
+        const double tx = ((double)ix + top24(w.z)) * a.edge64[0];
+        const double ty = ((double)iy + top24(w.w)) * a.edge64[1];
+        const double tz = ((double)iz + top24(q.x)) * a.edge64[2];
+        const double rad = 0.5 * a.Re * cbrt(top24(q.y));
+        const double ct = 2.0 * top24(q.z) - 1.0;
+        const double stt = sqrt(fmax(0.0, 1.0 - ct * ct));
+        const double ph = two_pi * top24(q.w);
+        const double cx = tx + rad * stt * cos(ph), cy = ty + rad * stt * sin(ph), cz = tz + rad * ct;
+        // centre of mass of the walk (bead 0 at the origin), then the beads
+        double sx = 0, sy = 0, sz = 0, x = 0, y = 0, z = 0;
+        for (int i = 1; i < N; ++i) {
+            const double3 b = gauss_bond(init_block((uint32_t)i, chain, 4u * (uint32_t)j + 2u, ia.sys_id, ia.seed),
+                                         ia.sigma);
+            x += b.x;
+            y += b.y;
+            z += b.z;
+            sx += x;
+            sy += y;
+            sz += z;
+        }
+        const double mx = sx / (double)N, my = sy / (double)N, mz = sz / (double)N;
+        ok = true;
+        x = y = z = 0;
+        for (int i = 0; i < N; ++i) {
+            if (i > 0) {
+                const double3 b = gauss_bond(
+                    init_block((uint32_t)i, chain, 4u * (uint32_t)j + 2u, ia.sys_id, ia.seed), ia.sigma);
+                x += b.x;
+                y += b.y;
+                z += b.z;
+            }
+            const double pz = cz + (z - mz);
+            if (ia.walls && !(pz >= zlo && pz <= zhi)) ok = false;
+            store_init(ia, base + i, cx + (x - mx), cy + (y - my), pz);
+        }
+        if (!ia.walls) break;
+    }
+    if (!ok) atomicOr(ia.status, ST_PLACEMENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -1490,6 +1810,12 @@ __global__ __launch_bounds__(256) void k_obs_cells(ObsArgs a)
             f = a.chiN * pa * pb + 0.5 * a.kappaN * inc * inc;
         else
             f = 0.5 * a.kappaN * inc * inc - 0.25 * a.chiN * (pa - pb) * (pa - pb);
+        if (a.umb_lambda > 0.0) {
+            // umbrella toward the target fields: (lambda/2) sum_t (phi_t - target_t)^2
+            const float2 t = a.tgt[a.cell_off + c];
+            const double da = pa - (double)t.x, db = pb - (double)t.y;
+            f += 0.5 * a.umb_lambda * (da * da + db * db);
+        }
         nadd(q[5], f);
     }
     block_reduce_store(q, a.partials, a.block_base + blockIdx.x);
@@ -1528,8 +1854,15 @@ static void launch_sweep_d(const SweepArgs &a, int blocks, hipStream_t st)
 {
     const dim3 g(blocks), b(64 * a.waves_per_block);
     const size_t lds = sizeof(uint32_t) * 2 * (DM == 2 ? kAggSlotsFaces : kAggSlotsCells) * a.waves_per_block;
-    if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC>), g, b, lds, st, a);
-    else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC>), g, b, lds, st, a);
+    // contexts without walls, zones, umbrella or caller-set classes launch
+    // kernels built without that code (fewer registers)
+    if (a.cpl) {
+        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, true>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true>), g, b, lds, st, a);
+    } else {
+        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, false>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false>), g, b, lds, st, a);
+    }
 }
 
 template <int R, int CW, bool SMC>
@@ -1664,6 +1997,24 @@ hipError_t launch_init(const InitArgs &a, hipStream_t st)
     const int blocks = (a.n_chains + 255) / 256;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_init_walks, dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+int64_t place_bsum_words(int64_t n_cells) { return (n_cells + kScan64Tile - 1) / kScan64Tile; }
+
+hipError_t launch_place(const PlaceArgs &a, unsigned long long *bsum, hipStream_t st)
+{
+    if (a.n_cells <= 0 || a.ia.n_chains <= 0) return hipSuccess;
+    const int cb = (int)((a.n_cells + 255) / 256);
+    hipLaunchKernelGGL(k_place_weights, dim3(cb), dim3(256), 0, st, a);
+    const int nb = (int)place_bsum_words(a.n_cells);
+    for (int k = 0; k < 2; ++k) {
+        unsigned long long *x = a.W + k * a.n_cells;
+        hipLaunchKernelGGL(k_scan64_partials, dim3(nb), dim3(kScan64Block), 0, st, x, a.n_cells, bsum);
+        hipLaunchKernelGGL(k_scan64_bsum, dim3(1), dim3(kScan64Block), 0, st, bsum, nb);
+        hipLaunchKernelGGL(k_scan64_apply, dim3(nb), dim3(kScan64Block), 0, st, x, a.n_cells, bsum);
+    }
+    hipLaunchKernelGGL(k_place_chains, dim3((a.ia.n_chains + 255) / 256), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -25,12 +25,16 @@ struct SweepArgs {
                                    // 2: face fluxes in flux buffer s mod 2, folded by k_fold_faces
     uint32_t *flux;                // mode 2: two buffers of three count_words-word arrays
     int smc;                       // some system uses bond-force-biased moves
+    int cpl;                       // some system uses walls, zones, the umbrella or caller-set classes
     const float2 *omega;           // frozen fields, per cell (A, B)
     const uint64_t *sweep_ctr;     // sweeps done before this graph / launch sequence
     uint32_t rel;                  // sweep index relative to *sweep_ctr
     uint64_t seed;
     unsigned long long *accept;    // [n_sys][kAcceptSlots][kAcceptStride]
     uint32_t *status;
+    uint8_t *chain_class;          // per logical chain: 0 = pattern a, 1 = pattern b
+    const float2 *tgt;             // umbrella target (phi_A, phi_B) per cell
+    unsigned long long *conv;      // [n_sys][2]: chains converted to class a, to class b
 };
 
 struct DensityArgs {
@@ -42,6 +46,7 @@ struct DensityArgs {
     int *C0, *C1, *C2;
     uint32_t *counts;              // the target buffer (zeroed by the caller)
     uint32_t *status;
+    const uint8_t *chain_class;
 };
 
 struct ReorderArgs {
@@ -67,6 +72,7 @@ struct FieldArgs {
     int64_t n_cells;
     const uint32_t *counts;        // current counts
     const float2 *omega;
+    const float2 *tgt;             // umbrella targets
     float *out;                    // [2][n_cells]
 };
 
@@ -81,6 +87,23 @@ struct InitArgs {
     double sigma;                  // Re / sqrt(3 (N - 1))
     float *P0, *P1, *P2;
     int *C0, *C1, *C2;
+    int walls, wall_lo, wall_hi;   // chains are drawn again until they fit between the walls
+    uint32_t *status;
+};
+
+// Placement from target concentration fields (one system).
+struct PlaceArgs {
+    InitArgs ia;                   // representation, stream, walls, output arrays
+    const DevSys *sys;             // the system's table entry
+    const uint32_t *chain_id;      // logical chain id per slot of the context
+    const uint8_t *chain_class;    // per logical chain of the context
+    int64_t chain_off, cell_off, n_cells;
+    int grid[3];
+    double edge64[3];              // box / grid in FP64 (target points)
+    double Re;
+    const float2 *tgt;             // target (phi_A, phi_B) per cell of the context
+    unsigned long long *W;         // [2][n_cells] inclusive prefix sums of the class weights
+    int na[2];                     // A beads of pattern a, b
 };
 
 struct ObsArgs {
@@ -96,6 +119,8 @@ struct ObsArgs {
     double phi_per_count;          // M / B
     double chiN, kappaN;
     int ham_form;
+    double umb_lambda;             // umbrella strength (0: off)
+    const float2 *tgt;             // umbrella targets per cell of the context
     double *partials;
     int block_base;
 };
@@ -133,5 +158,7 @@ hipError_t launch_iota_chains(const ReorderArgs &a, hipStream_t st);
 hipError_t launch_reorder(int repr, const ReorderArgs &a, hipStream_t st);
 int64_t reorder_bsum_words(int64_t total_cells);
 hipError_t launch_observables(int cw, const ObsArgs &a, double *out, hipStream_t st);
+hipError_t launch_place(const PlaceArgs &a, unsigned long long *scan_bsum, hipStream_t st);
+int64_t place_bsum_words(int64_t n_cells);
 
 }  // namespace soma

@@ -26,7 +26,12 @@ enum StatusBits : uint32_t {
     ST_COUNT_OVERFLOW = 1u,
     ST_CELL_OVERFLOW = 4u,
     ST_INTERNAL = 8u,
+    ST_PLACEMENT = 16u,     // a chain did not fit between the walls (initial walks, placement)
 };
+
+// Attempts of the initial walks and of the placement to draw a chain that
+// fits between walls.
+constexpr int kMaxAttempts = 64;
 
 // One system, as the kernels see it.  Offsets are in elements of the flat
 // arrays shared by all systems of a context.
@@ -62,6 +67,17 @@ struct alignas(16) DevSys {
     double smc_A;          // A
     double smc_s2A;        // sqrt(2 A)
     double k_spring;       // k in FP64 (the force of the proposal)
+    // Coupling (Sec. 3.2): umbrella potential toward target concentration
+    // fields, hard walls at z-cell faces, molecular-type conversion zones.
+    int32_t umb;           // 1: omega_t gains -umb_coef * target_t(c) (the lambda phi_t/N part is in the cXX)
+    float umb_coef;        // lambda / N
+    int32_t walls;         // 1: trial positions outside z cells [wall_lo, wall_hi) are rejected
+    int32_t wall_lo, wall_hi;
+    int32_t zones;         // 1: conversion zones at the walls
+    int32_t cls_array;     // 1: chain classes come from the class array (zones, or classes set by
+                           //    the caller); 0: chains [0, n_chains_a) are class a
+    int32_t zone_a, zone_b;            // lower / upper zone present
+    int32_t zone_a_lim, zone_b_lim;    // N (wall_lo + lower width), N (wall_hi - upper width)
     alignas(16) uint32_t pat_a[kPatternWords];   // bit i: type of bead i (0 = A, 1 = B)
     alignas(16) uint32_t pat_b[kPatternWords];
 };

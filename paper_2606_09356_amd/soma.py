@@ -37,7 +37,7 @@ class soma_system_desc(C.Structure):
                 ("ham_form", C.c_int32), ("pattern_a", C.c_void_p), ("pattern_b", C.c_void_p),
                 ("chiN", C.c_double), ("kappaN", C.c_double), ("Re", C.c_double),
                 ("box", C.c_double * 3), ("grid", C.c_int32 * 3), ("move_halfwidth", C.c_double),
-                ("smc_A", C.c_double)]
+                ("smc_A", C.c_double), ("walls", C.c_int32 * 2), ("zones", C.c_int32 * 2)]
 
 
 class soma_options(C.Structure):
@@ -45,14 +45,15 @@ class soma_options(C.Structure):
                 ("use_graph", C.c_int32), ("density_mode", C.c_int32), ("reorder_every", C.c_int32),
                 ("waves_per_block", C.c_int32), ("waves_per_cu", C.c_int32), ("sys_id_base", C.c_int32),
                 ("launch_order", C.c_int32),
-                ("hip_stream", C.c_void_p)]
+                ("hip_stream", C.c_void_p), ("coupling", C.c_int32)]
 
 
 class soma_obs(C.Structure):
     _fields_ = [("Re2", C.c_double), ("Re2_err", C.c_double), ("Rg2", C.c_double),
                 ("Rg2_err", C.c_double), ("Ebond_per_chain", C.c_double),
                 ("Enb_per_chain", C.c_double), ("accept_ratio", C.c_double),
-                ("n_moves", C.c_uint64), ("n_accepted", C.c_uint64), ("sweep", C.c_uint64)]
+                ("n_moves", C.c_uint64), ("n_accepted", C.c_uint64), ("sweep", C.c_uint64),
+                ("converted_to_a", C.c_uint64), ("converted_to_b", C.c_uint64)]
 
 
 class soma_info(C.Structure):
@@ -65,13 +66,20 @@ class soma_info(C.Structure):
 class soma_tune(C.Structure):
     _fields_ = [("waves_per_block", C.c_int32), ("waves_per_cu", C.c_int32), ("xcd_remap", C.c_int32),
                 ("density_mode", C.c_int32), ("n_candidates", C.c_int32), ("us_per_sweep", C.c_double),
-                ("us_per_sweep_before", C.c_double)]
+                ("us_per_sweep_before", C.c_double), ("from_cache", C.c_int32)]
+
+
+class soma_ktimes(C.Structure):
+    _fields_ = [("n_sweeps", C.c_int32), ("density_mode", C.c_int32), ("sweep_kernel_us", C.c_double),
+                ("fold_kernel_us", C.c_double), ("sweep_us", C.c_double)]
 
 
 EXPORTS = ("soma_workspace_size", "soma_create", "soma_destroy", "soma_mc_sweep", "soma_sync",
            "soma_density", "soma_fields", "soma_observables", "soma_get_positions",
            "soma_set_positions", "soma_get_state", "soma_set_state", "soma_set_fields",
-           "soma_release_fields", "soma_set_sweep", "soma_get_info", "soma_autotune", "soma_last_error")
+           "soma_release_fields", "soma_set_sweep", "soma_get_info", "soma_autotune", "soma_tune_cache_clear",
+           "soma_time_kernels", "soma_place_from_fields", "soma_set_umbrella", "soma_get_classes",
+           "soma_set_classes", "soma_last_error")
 
 _lib = None
 
@@ -108,6 +116,12 @@ def load_library(path: str = LIB_PATH):
         "soma_set_sweep": ([P, C.c_uint64], C.c_int),
         "soma_get_info": ([P, P], C.c_int),
         "soma_autotune": ([P, I32, P], C.c_int),
+        "soma_tune_cache_clear": ([], None),
+        "soma_time_kernels": ([P, I32, P], C.c_int),
+        "soma_place_from_fields": ([P, I32, P], C.c_int),
+        "soma_set_umbrella": ([P, I32, C.c_double], C.c_int),
+        "soma_get_classes": ([P, I32, P], C.c_int),
+        "soma_set_classes": ([P, I32, P], C.c_int),
         "soma_last_error": ([P], C.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -133,6 +147,8 @@ def _desc_array(systems: Sequence[SystemDesc]):
         d.grid = (C.c_int32 * 3)(*s.grid)
         d.move_halfwidth = s.move_halfwidth
         d.smc_A = float(getattr(s, "smc_A", 0.0))
+        d.walls = (C.c_int32 * 2)(*(getattr(s, "walls", None) or (0, 0)))
+        d.zones = (C.c_int32 * 2)(*(getattr(s, "zones", None) or (0, 0)))
     return arr, keep
 
 
@@ -142,7 +158,7 @@ class Soma:
     def __init__(self, systems: Sequence[SystemDesc], seed: int = 0, pos_repr: str = "f32",
                  count_width: int = 16, use_graph: bool = True, density_mode: int = 0,
                  reorder_every: int = 0, waves_per_block: int = 0, waves_per_cu: int = 0,
-                 sys_id_base: int = 0, launch_order: int = 0,
+                 sys_id_base: int = 0, launch_order: int = 0, coupling: bool = False,
                  device: str = "cuda:0", stream=None):
         import torch
         self._torch = torch
@@ -163,6 +179,7 @@ class Soma:
         o.waves_per_cu = waves_per_cu
         o.sys_id_base = sys_id_base
         o.launch_order = launch_order
+        o.coupling = int(bool(coupling))
         o.hip_stream = self.stream.cuda_stream
         self.options = o
         self.pos_repr = o.pos_repr
@@ -217,10 +234,17 @@ class Soma:
         return {f: getattr(i, f) for f, _ in soma_info._fields_}
 
     def autotune(self, trial_sweeps: int = 5) -> dict:
-        """Time every launch shape and keep the fastest; trial sweeps are undone."""
+        """Time every launch shape and keep the fastest (or take the cached
+        shape of a context with the same key); trial sweeps are undone."""
         t = soma_tune()
         self._c(self.lib.soma_autotune(self.ctx, trial_sweeps, C.byref(t)))
         return {f: getattr(t, f) for f, _ in soma_tune._fields_}
+
+    def time_kernels(self, n_sweeps: int = 5) -> dict:
+        """Run n real sweeps eagerly with HIP events around each kernel; average durations."""
+        t = soma_ktimes()
+        self._c(self.lib.soma_time_kernels(self.ctx, n_sweeps, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in soma_ktimes._fields_}
 
     def density(self, sys: int = 0) -> np.ndarray:
         M = self.systems[sys].n_cells
@@ -270,8 +294,30 @@ class Soma:
         w = np.ascontiguousarray(omega, dtype=np.float32).reshape(2, self.systems[sys].n_cells)
         self._c(self.lib.soma_set_fields(self.ctx, sys, w.ctypes.data))
 
+    def place_from_fields(self, sys: int, phi_target: np.ndarray):
+        """Place the chains of `sys` from target fields [2][M] (needs coupling=True)."""
+        t = np.ascontiguousarray(phi_target, dtype=np.float32).reshape(2, self.systems[sys].n_cells)
+        self._c(self.lib.soma_place_from_fields(self.ctx, sys, t.ctypes.data))
+
+    def set_umbrella(self, sys: int, lam: float):
+        self._c(self.lib.soma_set_umbrella(self.ctx, sys, float(lam)))
+
+    def classes(self, sys: int = 0) -> np.ndarray:
+        out = np.zeros(self.systems[sys].n_chains, np.uint8)
+        self._c(self.lib.soma_get_classes(self.ctx, sys, out.ctypes.data))
+        return out
+
+    def set_classes(self, sys: int, cls: np.ndarray):
+        c = np.ascontiguousarray(cls, dtype=np.uint8).reshape(self.systems[sys].n_chains)
+        self._c(self.lib.soma_set_classes(self.ctx, sys, c.ctypes.data))
+
     def set_sweep(self, sweep: int):
         self._c(self.lib.soma_set_sweep(self.ctx, sweep))
 
     def release_fields(self, sys: int):
         self._c(self.lib.soma_release_fields(self.ctx, sys))
+
+
+def tune_cache_clear():
+    """Empty the library's process-wide autotune cache."""
+    load_library().soma_tune_cache_clear()

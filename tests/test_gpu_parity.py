@@ -21,7 +21,7 @@ import pytest
 
 import oracle
 from paper_2606_09356_amd import workloads as W
-from paper_2606_09356_amd.soma import Soma, SomaError, SOMA_EOVERFLOW, SOMA_ESTATE, SOMA_ENONFINITE
+from paper_2606_09356_amd.soma import Soma, SomaError, SOMA_EOVERFLOW, SOMA_ESTATE, SOMA_ENONFINITE, tune_cache_clear
 from tests.helpers.closed_forms import acceptance_closed_form, two_bead_cell_probabilities
 
 pytestmark = pytest.mark.gpu
@@ -236,6 +236,7 @@ def test_autotune_keeps_the_trajectory(r):
     """Autotuning times every launch shape on trial sweeps and undoes them:
     the tuned context then continues exactly like an untuned one."""
     systems = W.batched_mixed(n_systems=4, seed=48, bead_range=(2000, 12000))
+    tune_cache_clear()
     a = Soma(systems, seed=SEED, pos_repr=r, count_width=16, reorder_every=3)
     b = Soma(systems, seed=SEED, pos_repr=r, count_width=16, reorder_every=3)
     a.sweep(2)
@@ -247,13 +248,45 @@ def test_autotune_keeps_the_trajectory(r):
     assert (i["waves_per_block"], i["waves_per_cu"], i["xcd_remap"], i["density_mode"]) == \
         (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"], t["density_mode"])
     assert i["sweep"] == 2
+    # a second context with the same key takes the cached shape without timing
+    c = Soma(systems, seed=SEED, pos_repr=r, count_width=16, reorder_every=3)
+    tc = c.autotune(trial_sweeps=2)
+    assert tc["from_cache"] == 1 and tc["n_candidates"] == 0
+    ic = c.info()
+    assert (ic["waves_per_block"], ic["waves_per_cu"], ic["xcd_remap"], ic["density_mode"]) == \
+        (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"], t["density_mode"])
+    c.sweep(2)
+    c.sweep(5)
     a.sweep(5)
     b.sweep(5)
     for k in range(len(systems)):
         assert _same_state(a.state(k), b.state(k)), k
         assert (a.density(k) == b.density(k)).all(), k
+        assert _same_state(c.state(k), b.state(k)), k
         oa, ob = a.observables(k), b.observables(k)
         assert (oa["n_moves"], oa["n_accepted"], oa["sweep"]) == (ob["n_moves"], ob["n_accepted"], ob["sweep"]), k
+    a.close()
+    b.close()
+    c.close()
+
+
+@pytest.mark.parametrize("dm", [0, 1, 2])
+def test_kernel_timing_sweeps_are_real_sweeps(dm):
+    """soma_time_kernels runs real sweeps (eager, with events around each
+    kernel): the trajectory equals plain sweeps, and the durations are positive."""
+    systems = W.batched_mixed(n_systems=4, seed=49, bead_range=(2000, 12000))
+    a = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, density_mode=dm, reorder_every=2)
+    b = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, density_mode=dm, reorder_every=2)
+    a.sweep(1)
+    t = a.time_kernels(3)
+    a.sweep(1)
+    b.sweep(5)
+    assert t["n_sweeps"] == 3 and t["density_mode"] == dm and t["sweep_kernel_us"] > 0
+    assert (t["fold_kernel_us"] > 0) == (dm != 1)
+    for k in range(len(systems)):
+        assert _same_state(a.state(k), b.state(k)), k
+        assert (a.density(k) == b.density(k)).all(), k
+        assert a.observables(k)["n_accepted"] == b.observables(k)["n_accepted"]
     a.close()
     b.close()
 
@@ -374,17 +407,30 @@ def test_two_bead_frozen_field_boltzmann_on_gpu():
     g.close()
 
 
+def apply_shape(g, shape):
+    """"auto": the benchmark's launch configuration (the autotuner's choice);
+    "dmK": the library's default shape in density mode K."""
+    if shape == "auto":
+        t = g.autotune(2)
+        print(f"[shape] autotuned: {t}", flush=True)
+    return g
+
+
+@pytest.mark.parametrize("shape", ["auto", "dm0", "dm1", "dm2"])
 @pytest.mark.parametrize("name", ["plain_large", "mixed_large"])
-def test_full_size_single_sweep_parity(name):
-    """Full-size workloads in the benchmark's launch configuration: every
-    bead's decision compared, mismatch rate <= 1e-6, density bit-exact."""
+def test_full_size_single_sweep_parity(name, shape):
+    """Full-size workloads, in the benchmark's launch configuration (the
+    autotuner's choice) and in each density mode: every bead's decision
+    compared, mismatch rate <= 1e-6, density bit-exact after each sweep."""
     systems = W.workload(name)
     opts = W.WORKLOAD_OPTIONS[name]
     r, cw = opts["pos_repr"], opts["count_width"]
     s = systems[0]
-    print(f"[full-size] {name}: {s.n_beads} beads", flush=True)
+    print(f"[full-size] {name} ({shape}): {s.n_beads} beads", flush=True)
     xyz = W.gaussian_walks(s, seed=11)
-    g = Soma(systems, seed=SEED, pos_repr=r, count_width=cw)
+    dm = int(shape[2]) if shape.startswith("dm") else 0
+    g = apply_shape(Soma(systems, seed=SEED, pos_repr=r, count_width=cw, density_mode=dm,
+                         reorder_every=opts["reorder_every"]), shape)
     g.set_positions(0, xyz)
     o = oracle.OracleSystem(s, sys_id=0, mode=oracle.MODE_F32 if r == "f32" else oracle.MODE_CELL)
     o.set_positions(xyz)
@@ -400,7 +446,8 @@ def test_full_size_single_sweep_parity(name):
         assert (g.density(0) == oracle_density_of_gpu_state(g, 0, o)).all()
         o.density()
         o.fields()
-    print(f"[full-size] {name}: {mism} differing beads of {total} decisions", flush=True)
+    print(f"[full-size] {name} ({shape}, density mode {g.info()['density_mode']}): "
+          f"{mism} differing beads of {total} decisions", flush=True)
     assert mism / total <= 1e-6, (mism, total)
     g.close()
 

@@ -12,7 +12,8 @@ the FP64 oracle, and sampled full-size parity of the batched workloads.
   oracle within 0.5 %, and Re^2, Rg^2 within two combined chain-level
   standard errors.
 * Full size, batched: one sweep of the 64- and 256-system workloads in the
-  benchmark's launch configuration; for sampled systems the oracle starts
+  benchmark's launch configuration (autotuned) and in density modes 1 and 2;
+  for sampled systems the oracle starts
   from the GPU's own stored state, and the density and the next stored
   state are compared bead by bead.
 """
@@ -100,13 +101,20 @@ def test_equilibrium_observables_agree_with_oracle(r):
     g.close()
 
 
+@pytest.mark.parametrize("shape", ["auto", "dm1", "dm2"])
 @pytest.mark.parametrize("name,sample", [("batched_uneven", [0, 17, 63]), ("batched_mixed", [0, 101, 255])])
-def test_full_size_batched_sampled_parity(name, sample):
+def test_full_size_batched_sampled_parity(name, sample, shape):
+    """One sweep of the full batched workloads in the benchmark's launch
+    configuration (autotuned) and in density modes 1 and 2."""
     systems = W.workload(name)
     opts = W.WORKLOAD_OPTIONS[name]
     r, cw = opts["pos_repr"], opts["count_width"]
-    print(f"[full-size] {name}: {len(systems)} systems, {sum(s.n_beads for s in systems)} beads", flush=True)
-    g = Soma(systems, seed=SEED, pos_repr=r, count_width=cw, reorder_every=opts["reorder_every"])
+    print(f"[full-size] {name} ({shape}): {len(systems)} systems, {sum(s.n_beads for s in systems)} beads",
+          flush=True)
+    dm = int(shape[2]) if shape.startswith("dm") else 0
+    g = Soma(systems, seed=SEED, pos_repr=r, count_width=cw, reorder_every=opts["reorder_every"], density_mode=dm)
+    if shape == "auto":
+        print(f"[shape] autotuned: {g.autotune(2)}", flush=True)
     g.sweep(3)
     mode = oracle.MODE_F32 if r == "f32" else oracle.MODE_CELL
     orcs = {}

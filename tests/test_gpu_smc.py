@@ -31,7 +31,8 @@ def mixed_batch(seed):
     return systems
 
 
-@pytest.mark.parametrize("r,cw,dm", [("f32", 16, 0), ("f32", 16, 1), ("cell", 32, 0), ("cell", 16, 1)])
+@pytest.mark.parametrize("r,cw,dm", [("f32", 16, 0), ("f32", 16, 1), ("f32", 16, 2), ("cell", 32, 0), ("cell", 16, 1),
+                                     ("cell", 16, 2), ("cell", 32, 2)])
 def test_smart_move_parity(r, cw, dm):
     systems = mixed_batch(61)
     print(f"[smc parity] {r}/u{cw}/mode {dm}: {sum(s.n_beads for s in systems)} beads", flush=True)
@@ -99,14 +100,20 @@ def test_smart_two_bead_frozen_field_boltzmann_on_gpu():
     g.close()
 
 
-def test_full_size_smart_move_parity():
-    """plain_large with smart moves, in the benchmark's configuration: every
-    decision of two sweeps compared with the oracle, density bit-exact."""
+@pytest.mark.parametrize("shape", ["auto", "dm0", "dm2"])
+def test_full_size_smart_move_parity(shape):
+    """plain_large with smart moves, in the benchmark's configuration (the
+    autotuner's choice) and in density modes 0 and 2: every decision of two
+    sweeps compared with the oracle, density bit-exact."""
     systems = W.workload("plain_large_smc")
     s = systems[0]
-    print(f"[full-size] plain_large_smc: {s.n_beads} beads", flush=True)
+    print(f"[full-size] plain_large_smc ({shape}): {s.n_beads} beads", flush=True)
     xyz = W.gaussian_walks(s, seed=11)
-    g = Soma(systems, seed=SEED, pos_repr="f32", count_width=16)
+    dm = int(shape[2]) if shape.startswith("dm") else 0
+    g = Soma(systems, seed=SEED, pos_repr="f32", count_width=16, density_mode=dm,
+             reorder_every=W.WORKLOAD_OPTIONS["plain_large_smc"]["reorder_every"])
+    if shape == "auto":
+        print(f"[shape] autotuned: {g.autotune(2)}", flush=True)
     g.set_positions(0, xyz)
     o = oracle.OracleSystem(s, sys_id=0, mode=oracle.MODE_F32)
     o.set_positions(xyz)
