@@ -239,6 +239,19 @@ int soma_fields(soma_ctx *ctx, int32_t sys, float *dst, int32_t dst_on_device);
  * bad index or null out, latched device errors as soma_density. */
 int soma_observables(soma_ctx *ctx, int32_t sys, soma_obs *out);
 
+/* soma_observables for callers that cannot allocate memory -- code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc:
+ * the same results, bit for bit, computed by the same kernels, with the
+ * partial sums in a static device array of the library (1 MiB per GPU, held
+ * until the process ends) instead of the context's workspace.  Makes no
+ * device or host allocation.  Limit: ceil(n_chains/256) + ceil(n_cells/256)
+ * <= 10922 for the system (SOMA_EINVAL beyond).  The context's device must
+ * be current (SOMA_EINVAL otherwise).  Calls on one GPU share the array:
+ * calls that overlap in time on one GPU (other threads, other streams) race
+ * and must be serialised by the caller.  Synchronises the context's stream;
+ * errors as soma_observables. */
+int soma_observables_noalloc(soma_ctx *ctx, int32_t sys, soma_obs *out);
+
 /* Unwrapped FP64 positions of system `sys` as host double [3][n_chains*N]
  * (chain-major, Re units).  Synchronises. */
 int soma_get_positions(soma_ctx *ctx, int32_t sys, double *xyz);

@@ -25,6 +25,31 @@ using soma::Tile;
 namespace {
 
 thread_local std::string g_create_error;
+constexpr size_t kErrCapacity = 512;   // bytes reserved for a context's error text
+
+// Device scratch of soma_observables_noalloc: the per-block partial sums and
+// the result of the observable reductions.  One array per GPU (each device
+// holds its own copy at its own address), kept until the process ends; the
+// host reaches it only through the address hipGetSymbolAddress returns.
+constexpr size_t kScratchDoubles = size_t(1) << 17;   // 1 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on device dev (current), resolved once per
+// device; nullptr if the runtime cannot resolve it.
+double *scratch_for_device(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
 
 struct Layout {
     size_t systems, tiles, chain_id, chain_id2, P[3], C[3], Q[3], D[3], keys, hist, bsum, perm, base, delta, flux, chunks,
@@ -66,6 +91,8 @@ struct soma_ctx {
     hipStream_t capture_stream = nullptr;
     int repr = 0, cw = 0, waves_per_block = 4, xcd_remap = 1, density_mode = 0, max_blocks = 0;
     int waves_per_cu = 0, n_cus = 0;
+    int device = 0;                    // the GPU the context was created on
+    double *scratch_dev = nullptr;     // that GPU's static scratch (soma_observables_noalloc)
     // density_mode 1 keeps the counts in rotation (base[(s+1)&1] + delta[(s+2)%3]
     // before sweep s); `rot` says the buffers are in that layout.  Otherwise
     // (canonical) the counts are base[0] and every delta is zero.
@@ -118,16 +145,21 @@ struct soma_ctx {
 
 namespace {
 
-int fail(soma_ctx *c, int code, const std::string &msg)
+// Error text goes into the context's string, whose capacity is reserved at
+// creation, so reporting an error on a context allocates nothing.
+int fail(soma_ctx *c, int code, const char *msg)
 {
-    if (c) c->err = msg;
+    if (c) c->err.assign(msg);
     else g_create_error = msg;
     return code;
 }
 
+int fail(soma_ctx *c, int code, const std::string &msg) { return fail(c, code, msg.c_str()); }
+
 int hip_fail(soma_ctx *c, hipError_t e, const char *where)
 {
-    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    char m[kErrCapacity];
+    std::snprintf(m, sizeof m, "%s: %s", where, hipGetErrorString(e));
     if (c) c->latched = SOMA_EDEVICE;
     return fail(c, SOMA_EDEVICE, m);
 }
@@ -834,6 +866,65 @@ int run_sweeps(soma_ctx *c, int32_t n, hipEvent_t *ev)
     return SOMA_OK;
 }
 
+// The observables of one system, with the block partial sums in `partials`
+// (12 doubles per block: ceil(n_chains/256) + ceil(n_cells/256) blocks) and
+// the six sums in `result`; allocates nothing.
+int observables_into(soma_ctx *c, int32_t sys, soma_obs *out, double *partials, double *result)
+{
+    int rc = canonicalize(c);
+    if (rc != SOMA_OK) return rc;
+    const HostSys &h = c->sys[sys];
+    soma::ObsArgs a{};
+    a.repr = c->repr;
+    a.n_chains = h.d.n_chains;
+    a.N = h.d.N;
+    a.stride = 2 * h.dev.P;
+    a.slot_off = h.dev.slot_off;
+    for (int d = 0; d < 3; ++d) {
+        a.edge[d] = h.dev.edge[d];
+        (&a.P0)[d] = c->P(d);
+        (&a.C0)[d] = c->C(d);
+    }
+    a.k_half = 1.5 * (h.d.N - 1) / (h.d.Re * h.d.Re);
+    a.counts = c->counts();
+    a.cell_off = h.dev.cell_off;
+    a.n_cells = h.dev.n_cells;
+    const double B = (double)h.d.n_chains * h.d.N;
+    a.phi_per_count = (double)h.dev.n_cells / B;
+    a.chiN = h.d.chiN;
+    a.kappaN = h.d.kappaN;
+    a.ham_form = h.d.ham_form;
+    a.umb_lambda = h.dev.umb ? h.umb_lambda : 0.0;
+    a.tgt = c->tgt();
+    a.partials = partials;
+    a.block_base = 0;
+    HIPCHK(c, soma::launch_observables(c->cw, a, result, c->stream));
+    double q[6];
+    unsigned long long conv[2] = {0, 0};
+    unsigned long long slots[soma::kAcceptSlots * soma::kAcceptStride];
+    HIPCHK(c, hipMemcpyAsync(q, result, sizeof q, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(conv, c->conv() + 2 * (size_t)sys, sizeof conv, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(slots, c->accept() + (size_t)sys * soma::kAcceptSlots * soma::kAcceptStride,
+                             sizeof slots, hipMemcpyDeviceToHost, c->stream));
+    if ((rc = sync_status(c)) != SOMA_OK) return rc;
+    unsigned long long acc = 0;
+    for (int k = 0; k < soma::kAcceptSlots; ++k) acc += slots[(size_t)k * soma::kAcceptStride];
+    const double n = (double)h.d.n_chains;
+    out->Re2 = q[0] / n;
+    out->Re2_err = std::sqrt(std::max(q[1] / n - out->Re2 * out->Re2, 0.0) / n);
+    out->Rg2 = q[2] / n;
+    out->Rg2_err = std::sqrt(std::max(q[3] / n - out->Rg2 * out->Rg2, 0.0) / n);
+    out->Ebond_per_chain = q[4] / n;
+    out->Enb_per_chain = (B / (double)h.dev.n_cells) / h.d.N * q[5] / n;
+    out->sweep = c->sweep;
+    out->n_moves = (uint64_t)(c->swept * (uint64_t)B);
+    out->n_accepted = acc;
+    out->accept_ratio = out->n_moves ? (double)acc / (double)out->n_moves : 0.0;
+    out->converted_to_a = conv[0];
+    out->converted_to_b = conv[1];
+    return SOMA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -884,6 +975,9 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
             return fail(nullptr, SOMA_EDEVICE, "cannot query the compute-unit count");
         }
         c->n_cus = cus;
+        c->device = dev;
+        c->scratch_dev = scratch_for_device(dev);
+        c->err.reserve(kErrCapacity);
     }
     set_shape(c, c->waves_per_block, opt->waves_per_cu, opt->launch_order == 0 ? 1 : 0);
     c->ws = static_cast<char *>(workspace);
@@ -1042,57 +1136,25 @@ int soma_observables(soma_ctx *c, int32_t sys, soma_obs *out)
     if (rc != SOMA_OK) return rc;
     if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
     if (!out) return fail(c, SOMA_EINVAL, "out is null");
-    if ((rc = canonicalize(c)) != SOMA_OK) return rc;
+    return observables_into(c, sys, out, c->partials(), c->obs_out());
+}
+
+int soma_observables_noalloc(soma_ctx *c, int32_t sys, soma_obs *out)
+{
+    int rc = check_ctx(c);
+    if (rc != SOMA_OK) return rc;
+    if ((rc = check_sys(c, sys)) != SOMA_OK) return rc;
+    if (!out) return fail(c, SOMA_EINVAL, "out is null");
+    if (!c->scratch_dev) return fail(c, SOMA_EDEVICE, "the static device scratch could not be resolved");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+        return fail(c, SOMA_EINVAL, "the context's device must be the current device");
     const HostSys &h = c->sys[sys];
-    soma::ObsArgs a{};
-    a.repr = c->repr;
-    a.n_chains = h.d.n_chains;
-    a.N = h.d.N;
-    a.stride = 2 * h.dev.P;
-    a.slot_off = h.dev.slot_off;
-    for (int d = 0; d < 3; ++d) {
-        a.edge[d] = h.dev.edge[d];
-        (&a.P0)[d] = c->P(d);
-        (&a.C0)[d] = c->C(d);
-    }
-    a.k_half = 1.5 * (h.d.N - 1) / (h.d.Re * h.d.Re);
-    a.counts = c->counts();
-    a.cell_off = h.dev.cell_off;
-    a.n_cells = h.dev.n_cells;
-    const double B = (double)h.d.n_chains * h.d.N;
-    a.phi_per_count = (double)h.dev.n_cells / B;
-    a.chiN = h.d.chiN;
-    a.kappaN = h.d.kappaN;
-    a.ham_form = h.d.ham_form;
-    a.umb_lambda = h.dev.umb ? h.umb_lambda : 0.0;
-    a.tgt = c->tgt();
-    a.partials = c->partials();
-    a.block_base = 0;
-    HIPCHK(c, soma::launch_observables(c->cw, a, c->obs_out(), c->stream));
-    double q[6];
-    unsigned long long conv[2] = {0, 0};
-    std::vector<unsigned long long> slots((size_t)soma::kAcceptSlots * soma::kAcceptStride);
-    HIPCHK(c, hipMemcpyAsync(q, c->obs_out(), sizeof q, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(conv, c->conv() + 2 * (size_t)sys, sizeof conv, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(slots.data(), c->accept() + (size_t)sys * slots.size(),
-                             sizeof(unsigned long long) * slots.size(), hipMemcpyDeviceToHost, c->stream));
-    if ((rc = sync_status(c)) != SOMA_OK) return rc;
-    unsigned long long acc = 0;
-    for (int k = 0; k < soma::kAcceptSlots; ++k) acc += slots[(size_t)k * soma::kAcceptStride];
-    const double n = (double)h.d.n_chains;
-    out->Re2 = q[0] / n;
-    out->Re2_err = std::sqrt(std::max(q[1] / n - out->Re2 * out->Re2, 0.0) / n);
-    out->Rg2 = q[2] / n;
-    out->Rg2_err = std::sqrt(std::max(q[3] / n - out->Rg2 * out->Rg2, 0.0) / n);
-    out->Ebond_per_chain = q[4] / n;
-    out->Enb_per_chain = (B / (double)h.dev.n_cells) / h.d.N * q[5] / n;
-    out->sweep = c->sweep;
-    out->n_moves = (uint64_t)(c->swept * (uint64_t)B);
-    out->n_accepted = acc;
-    out->accept_ratio = out->n_moves ? (double)acc / (double)out->n_moves : 0.0;
-    out->converted_to_a = conv[0];
-    out->converted_to_b = conv[1];
-    return SOMA_OK;
+    const size_t blocks = (size_t)(h.d.n_chains + 255) / 256 + (size_t)(h.dev.n_cells + 255) / 256;
+    if (12 * blocks > kScratchDoubles - 8)
+        return fail(c, SOMA_EINVAL, "system too large for the static scratch: ceil(n_chains/256) + "
+                                    "ceil(n_cells/256) must be at most 10922 blocks");
+    return observables_into(c, sys, out, c->scratch_dev, c->scratch_dev + (kScratchDoubles - 8));
 }
 
 int soma_get_positions(soma_ctx *c, int32_t sys, double *xyz)

@@ -79,7 +79,7 @@ EXPORTS = ("soma_workspace_size", "soma_create", "soma_destroy", "soma_mc_sweep"
            "soma_set_positions", "soma_get_state", "soma_set_state", "soma_set_fields",
            "soma_release_fields", "soma_set_sweep", "soma_get_info", "soma_autotune", "soma_tune_cache_clear",
            "soma_time_kernels", "soma_place_from_fields", "soma_set_umbrella", "soma_get_classes",
-           "soma_set_classes", "soma_last_error")
+           "soma_set_classes", "soma_observables_noalloc", "soma_last_error")
 
 _lib = None
 
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
         "soma_density": ([P, I32, P, I32], C.c_int),
         "soma_fields": ([P, I32, P, I32], C.c_int),
         "soma_observables": ([P, I32, P], C.c_int),
+        "soma_observables_noalloc": ([P, I32, P], C.c_int),
         "soma_get_positions": ([P, I32, P], C.c_int),
         "soma_set_positions": ([P, I32, P], C.c_int),
         "soma_get_state": ([P, I32, P, P], C.c_int),
