@@ -84,9 +84,9 @@ enum { SOMA_HAM_HELFAND = 0, SOMA_HAM_CHI_AB = 1 };
  * move_halfwidth below 0.99 cell edges box[d]/grid[d]; smc_A zero, or
  * positive with sqrt(2 smc_A) at most half a cell edge.
  *
- * Walls and boundary zones (Sec. 3.2, "Coupling": the SOMA subdomain keeps
- * fixed boundary fluxes by wall confinement and converts molecules in
- * boundary zones): walls = {lo, hi} with 0 <= lo < hi <= grid[2] puts hard
+ * Walls and boundary zones (Sec. 3.2, "Coupling": the particle subdomain
+ * holds the fluxes across its edges by confining beads with walls and by
+ * changing the type of molecules in zones next to them): walls = {lo, hi} with 0 <= lo < hi <= grid[2] puts hard
  * walls at the z-cell faces lo and hi -- a trial move whose z cell leaves
  * [lo, hi) is rejected, and initial walks and placements draw chains again
  * until every bead lies between the walls (64 attempts, else SOMA_EINVAL);
@@ -145,6 +145,12 @@ typedef struct {
     int32_t coupling;          /* nonzero: reserve workspace for target concentration fields
                                   (soma_place_from_fields, soma_set_umbrella): 8 B per cell
                                   plus 16 B per cell of the largest system */
+    int32_t packed_tiles;      /* 1: each workgroup moves floor(64 W / P) whole chains packed over
+                                  its W waves (P = ceil(N/2) lanes per chain), so fewer lanes
+                                  idle when 64 is not a multiple of P; chains spanning two waves
+                                  exchange their boundary beads through LDS.  Needs
+                                  waves_per_cu = 0 and no conversion zones. 0: G = floor(64/P)
+                                  chains per wave */
 } soma_options;
 
 typedef struct {
@@ -171,6 +177,7 @@ typedef struct {
     int32_t waves_per_block;   /* launch shape in use (see soma_autotune) */
     int32_t waves_per_cu;
     int32_t xcd_remap;
+    int32_t packed_tiles;      /* sweep launched over block tiles */
 } soma_info;
 
 /* Bytes of device workspace that soma_create needs for these systems. */
@@ -280,8 +287,8 @@ int soma_release_fields(soma_ctx *ctx, int32_t sys);
 
 /* Place the chains of system `sys` so that they reproduce target
  * concentration fields, the start of a SOMA run in the coupled workflow
- * (Sec. 3.2, "Coupling": molecules are placed within half a mean
- * end-to-end distance of their target positions).  phi_target: host float
+ * (Sec. 3.2, "Coupling": each molecule starts near a target position, at
+ * most half the mean end-to-end distance away).  phi_target: host float
  * [2][nx][ny][nz] (phi_A then phi_B, each in [0, 4096]).  A chain of class k
  * (A fraction f_k of its pattern) draws a target cell with probability
  * proportional to the integer weight floor(2^20 (f_k phi_A + (1 - f_k) phi_B)
@@ -317,9 +324,10 @@ int soma_get_info(soma_ctx *ctx, soma_info *out);
 
 /* Launch-shape autotuning, the "adjusting launch configurations" step of
  * the SOMA optimisation (Sec. 2.2).  For every candidate shape -- waves per
- * workgroup in {1, 2, 4, 8, 16}; one tile per wave, or a resident grid of
- * 8 or 32 waves per compute unit walking tile ranges; XCD-aware block order
- * on or off; density mode 0, 1 or 2 -- times `trial_sweeps` sweeps (1..1000)
+ * workgroup in {1, 2, 4, 8, 16}; one tile per wave, a resident grid of 8 or
+ * 32 waves per compute unit walking tile ranges, or one block tile per
+ * workgroup; XCD-aware block order on or off; density mode 0, 1 or 2 (not 2
+ * with conversion zones) -- times `trial_sweeps` sweeps (1..1000)
  * after one warm-up sweep, and keeps the fastest for every later sweep.  The trial
  * sweeps are undone: positions, counts, acceptance counters, the status
  * word and the sweep counter are restored, so the trajectory is exactly
@@ -334,6 +342,7 @@ typedef struct {
     double us_per_sweep;       /* trial time of the chosen shape (0 when from_cache) */
     double us_per_sweep_before;/* trial time of the shape in use at the call (0 when from_cache) */
     int32_t from_cache;        /* 1: the shape came from the process-wide cache, nothing was timed */
+    int32_t packed_tiles;      /* chosen tiling (see soma_options.packed_tiles) */
 } soma_tune;
 int soma_autotune(soma_ctx *ctx, int32_t trial_sweeps, soma_tune *out);
 

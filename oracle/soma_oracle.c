@@ -655,8 +655,9 @@ int orc_init_walks(const orc_system *s, uint64_t seed, double *xyz)
 /* ------------------------------------------------------------------------ */
 /* Placement from target concentration fields (Sec. 3.2, "Coupling")        */
 /* ------------------------------------------------------------------------ */
-/* Each molecule is placed within half a mean end-to-end distance of a
- * target position that follows the supplied concentration fields:
+/* Every molecule starts with its centre of mass at most Re/2 (half the
+ * ideal end-to-end distance) from a target position drawn from the supplied
+ * concentration fields:
  *   1. chains of class k (pattern a or b, with A fraction f_k) draw a target
  *      cell with probability proportional to the integer weight
  *      w_k(c) = floor(2^20 (f_k tA(c) + (1 - f_k) tB(c)) + 1/2), through the

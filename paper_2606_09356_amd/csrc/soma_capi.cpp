@@ -54,7 +54,7 @@ double *scratch_for_device(int dev)
 struct Layout {
     size_t systems, tiles, chain_id, chain_id2, P[3], C[3], Q[3], D[3], keys, hist, bsum, perm, base, delta, flux, chunks,
         omega, accept, status, partials, obs_out, staging, chain_class, chain_class2, conv, tgt, place_W, place_bsum,
-        total;   // base: counts, delta: density delta
+        ptiles, total;   // base: counts, delta: density delta; ptiles: block tiles
     int64_t total_slots = 0, total_cells = 0, total_chains = 0, count_words = 0;
     int n_tiles = 0;
     int n_chunks = 0;      // fold chunks of density mode 2
@@ -91,6 +91,9 @@ struct soma_ctx {
     hipStream_t capture_stream = nullptr;
     int repr = 0, cw = 0, waves_per_block = 4, xcd_remap = 1, density_mode = 0, max_blocks = 0;
     int waves_per_cu = 0, n_cus = 0;
+    int packed = 0;                    // sweep launched over block tiles
+    int n_ptiles = 0;
+    std::vector<Tile> ptiles_host;     // the block tiles of the current waves_per_block
     int device = 0;                    // the GPU the context was created on
     double *scratch_dev = nullptr;     // that GPU's static scratch (soma_observables_noalloc)
     // density_mode 1 keeps the counts in rotation (base[(s+1)&1] + delta[(s+2)%3]
@@ -115,6 +118,7 @@ struct soma_ctx {
 
     DevSys *d_sys() const { return reinterpret_cast<DevSys *>(ws + L.systems); }
     Tile *d_tiles() const { return reinterpret_cast<Tile *>(ws + L.tiles); }
+    Tile *d_ptiles() const { return reinterpret_cast<Tile *>(ws + L.ptiles); }
     float *P(int d) const { return reinterpret_cast<float *>(ws + L.P[d]); }
     int *C(int d) const { return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + L.C[d]) : nullptr; }
     float *Q(int d) const { return reinterpret_cast<float *>(ws + L.Q[d]); }
@@ -181,6 +185,10 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
     if (opt->density_mode < 0 || opt->density_mode > 2) { msg = "density_mode must be 0, 1 or 2"; return SOMA_EINVAL; }
     if (opt->reorder_every < 0) { msg = "reorder_every must be >= 0"; return SOMA_EINVAL; }
     if (opt->launch_order != 0 && opt->launch_order != 1) { msg = "launch_order must be 0 or 1"; return SOMA_EINVAL; }
+    if (opt->packed_tiles != 0 && opt->packed_tiles != 1) { msg = "packed_tiles must be 0 or 1"; return SOMA_EINVAL; }
+    if (opt->packed_tiles && opt->waves_per_cu > 0) { msg = "packed_tiles needs waves_per_cu = 0"; return SOMA_EINVAL; }
+    for (int32_t k = 0; k < n_sys && opt->packed_tiles; ++k)
+        if (sys[k].zones[0] > 0 || sys[k].zones[1] > 0) { msg = "packed_tiles is not available with conversion zones"; return SOMA_EINVAL; }
     if (opt->sys_id_base < 0 || (int64_t)opt->sys_id_base + n_sys >= (int64_t(1) << 31)) { msg = "sys_id_base + n_sys must stay below 2^31"; return SOMA_EINVAL; }
     for (int32_t k = 0; k < n_sys; ++k) {
         const soma_system_desc &d = sys[k];
@@ -327,6 +335,7 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     L.systems = take(sizeof(DevSys) * n_sys);
     L.tiles = take(sizeof(Tile) * tiles);
+    L.ptiles = take(sizeof(Tile) * tiles);     // block tiles never outnumber wave tiles
     L.chain_id = take(sizeof(uint32_t) * chains);
     L.chain_id2 = take(sizeof(uint32_t) * chains);
     for (int a = 0; a < 3; ++a) L.P[a] = take(sizeof(float) * slots);
@@ -398,12 +407,37 @@ int sync_status(soma_ctx *c)
 
 // Launch shape of the sweep kernel: waves per workgroup, resident grid
 // (waves per compute unit, 0 for one tile per wave) and block order.
-void set_shape(soma_ctx *c, int waves_per_block, int waves_per_cu, int xcd_remap)
+void set_shape(soma_ctx *c, int waves_per_block, int waves_per_cu, int xcd_remap, int packed = 0)
 {
     c->waves_per_block = waves_per_block;
     c->waves_per_cu = waves_per_cu;
     c->xcd_remap = xcd_remap;
     c->max_blocks = waves_per_cu > 0 ? std::max(1, waves_per_cu * c->n_cus / waves_per_block) : 0;
+    c->packed = packed && waves_per_cu == 0 && !c->any_zones ? 1 : 0;
+}
+
+// Block tiles for the current waves per block: floor(64 W / P) whole chains
+// of one system per tile.  Uploaded before the next sweep launch.
+int upload_block_tiles(soma_ctx *c)
+{
+    if (!c->packed) return SOMA_OK;
+    std::vector<Tile> t;
+    const int lanes = 64 * c->waves_per_block;
+    for (size_t k = 0; k < c->sys.size(); ++k) {
+        const int Gw = lanes / c->sys[k].dev.P;
+        for (int ch = 0; ch < c->sys[k].d.n_chains; ch += Gw) t.push_back(Tile{(uint32_t)k, (uint32_t)ch});
+    }
+    if ((int)t.size() > c->L.n_tiles) return fail(c, SOMA_EDEVICE, "block tile table overflow");
+    if (t.size() == c->ptiles_host.size() && c->n_ptiles == (int)t.size() &&
+        std::equal(t.begin(), t.end(), c->ptiles_host.begin(),
+                   [](const Tile &x, const Tile &y) { return x.sys == y.sys && x.chain0 == y.chain0; }))
+        return SOMA_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));     // the previous table may still be in flight
+    c->ptiles_host = std::move(t);
+    c->n_ptiles = (int)c->ptiles_host.size();
+    HIPCHK(c, hipMemcpyAsync(c->d_ptiles(), c->ptiles_host.data(), sizeof(Tile) * c->ptiles_host.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    return SOMA_OK;
 }
 
 // Key of the autotune cache: representation, count width, move kinds,
@@ -458,6 +492,9 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
     a.systems = c->d_sys();
     a.tiles = c->d_tiles();
     a.n_tiles = c->L.n_tiles;
+    a.ptiles = c->d_ptiles();
+    a.n_ptiles = c->n_ptiles;
+    a.packed = c->packed;
     a.waves_per_block = c->waves_per_block;
     a.max_blocks = c->max_blocks;
     a.xcd_remap = c->xcd_remap;
@@ -837,6 +874,7 @@ int run_sweeps(soma_ctx *c, int32_t n, hipEvent_t *ev)
 {
     int rc = SOMA_OK;
     if (n > 0 && (rc = sweep_layout(c)) != SOMA_OK) return rc;
+    if (n > 0 && (rc = upload_block_tiles(c)) != SOMA_OK) return rc;
     const uint64_t R = (uint64_t)c->opt.reorder_every;
     int32_t left = n;
     while (left > 0) {
@@ -979,7 +1017,7 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
         c->scratch_dev = scratch_for_device(dev);
         c->err.reserve(kErrCapacity);
     }
-    set_shape(c, c->waves_per_block, opt->waves_per_cu, opt->launch_order == 0 ? 1 : 0);
+    set_shape(c, c->waves_per_block, opt->waves_per_cu, opt->launch_order == 0 ? 1 : 0, opt->packed_tiles);
     c->ws = static_cast<char *>(workspace);
     for (size_t k = 0; k < c->sys.size(); ++k) {
         const HostSys &h = c->sys[k];
@@ -1446,6 +1484,7 @@ int soma_get_info(soma_ctx *c, soma_info *out)
     out->waves_per_block = c->waves_per_block;
     out->waves_per_cu = c->waves_per_cu;
     out->xcd_remap = c->xcd_remap;
+    out->packed_tiles = c->packed;
     return SOMA_OK;
 }
 
@@ -1472,7 +1511,7 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
         if (found) {
             // leave the rotation of density mode 1 before switching modes
             if ((rc = canonicalize(c)) != SOMA_OK) return rc;
-            set_shape(c, hit.waves_per_block, hit.waves_per_cu, hit.xcd_remap);
+            set_shape(c, hit.waves_per_block, hit.waves_per_cu, hit.xcd_remap, hit.packed_tiles);
             c->density_mode = hit.density_mode;
             drop_graphs(c);
             hit.n_candidates = 0;
@@ -1543,12 +1582,13 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
         }
         return SOMA_OK;
     };
-    auto time_shape = [&](int wpb, int wpcu, int xcd, int dm, double &us) -> int {
+    auto time_shape = [&](int wpb, int wpcu, int xcd, int dm, int pk, double &us) -> int {
         if ((rc = restore()) != SOMA_OK) return rc;
-        set_shape(c, wpb, wpcu, xcd);
+        set_shape(c, wpb, wpcu, xcd, pk);
         c->density_mode = dm;
         drop_graphs(c);
         if ((rc = sweep_layout(c)) != SOMA_OK) return rc;
+        if ((rc = upload_block_tiles(c)) != SOMA_OK) return rc;
         if ((rc = batch()) != SOMA_OK) return rc;
         HIPCHK(c, hipEventRecord(e0, c->stream));
         if ((rc = batch()) != SOMA_OK) return rc;
@@ -1559,32 +1599,37 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
         us = 1e3 * (double)ms / trial_sweeps;
         return SOMA_OK;
     };
-    soma_tune best{c->waves_per_block, c->waves_per_cu, c->xcd_remap, c->density_mode, 0, 0.0, 0.0, 0};
-    rc = time_shape(best.waves_per_block, best.waves_per_cu, best.xcd_remap, best.density_mode,
+    soma_tune best{c->waves_per_block, c->waves_per_cu, c->xcd_remap, c->density_mode, 0, 0.0, 0.0, 0, c->packed};
+    rc = time_shape(best.waves_per_block, best.waves_per_cu, best.xcd_remap, best.density_mode, best.packed_tiles,
                     best.us_per_sweep_before);
     best.us_per_sweep = best.us_per_sweep_before;
-    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32}, kXcd[] = {1, 0}, kDm[] = {0, 1, 2};
+    // wave tiles: one per wave, or resident grids of 8 or 32 waves per CU;
+    // block tiles (-1 here): one per block
+    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32, -1}, kXcd[] = {1, 0}, kDm[] = {0, 1, 2};
     for (int dm : kDm)
         for (int wpb : kWpb)
             for (int wpcu : kWpcu)
                 for (int xcd : kXcd) {
                     if (rc != SOMA_OK) break;
                     if (dm == 2 && c->any_zones) continue;   // conversions need cell words
+                    if (wpcu < 0 && (c->any_zones || wpb == 1)) continue;   // one wave: the same tiles
+                    const int pk = wpcu < 0 ? 1 : 0, cu = wpcu < 0 ? 0 : wpcu;
                     double us = 0.0;
-                    rc = time_shape(wpb, wpcu, xcd, dm, us);
+                    rc = time_shape(wpb, cu, xcd, dm, pk, us);
                     ++best.n_candidates;
                     if (rc == SOMA_OK && us < best.us_per_sweep) {
                         best.us_per_sweep = us;
                         best.waves_per_block = wpb;
-                        best.waves_per_cu = wpcu;
+                        best.waves_per_cu = cu;
                         best.xcd_remap = xcd;
                         best.density_mode = dm;
+                        best.packed_tiles = pk;
                     }
                 }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SOMA_OK) return rc;
-    set_shape(c, best.waves_per_block, best.waves_per_cu, best.xcd_remap);
+    set_shape(c, best.waves_per_block, best.waves_per_cu, best.xcd_remap, best.packed_tiles);
     c->density_mode = best.density_mode;
     drop_graphs(c);
 

@@ -101,6 +101,15 @@ __device__ __forceinline__ int wrap_step(int i, int n)
     return i >= n ? i - n : i;
 }
 
+// Wrap of any unwrapped index: beads are almost always within one image of
+// the box, where two compares suffice; the general form runs only for the
+// lanes that need it.
+__device__ __forceinline__ int wrap_any(int i, int n, float inv_n)
+{
+    if (i >= -n && i < 2 * n) return wrap_step(i, n);
+    return wrap_cell(i, n, inv_n);
+}
+
 // ---------------------------------------------------------------------------
 // Position representations
 // ---------------------------------------------------------------------------
@@ -142,11 +151,13 @@ __device__ __forceinline__ float3 bond(const BeadF32 &a, const BeadF32 &b, const
 {
     return make_float3(a.x - b.x, a.y - b.y, a.z - b.z);
 }
+// (the product of a small cell difference and the edge is exact, so the
+// fused form rounds exactly like the separate multiply and add)
 __device__ __forceinline__ float3 bond(const BeadCell &a, const BeadCell &b, const SysView &v)
 {
-    return make_float3((float)(a.cx - b.cx) * v.e0 + (a.ox - b.ox),
-                       (float)(a.cy - b.cy) * v.e1 + (a.oy - b.oy),
-                       (float)(a.cz - b.cz) * v.e2 + (a.oz - b.oz));
+    return make_float3(fmaf((float)(a.cx - b.cx), v.e0, a.ox - b.ox),
+                       fmaf((float)(a.cy - b.cy), v.e1, a.oy - b.oy),
+                       fmaf((float)(a.cz - b.cz), v.e2, a.oz - b.oz));
 }
 
 __device__ __forceinline__ BeadF32 propose(const BeadF32 &a, const Draw &d, const SysView &)
@@ -162,12 +173,25 @@ __device__ __forceinline__ void renorm(int &c, float &o, float e)
     while (o >= e) { o = o - e; c += 1; }
 }
 
+// renorm for a trial offset o + d with |d| < 0.99 edge: at most one step
+// down and one step up, each the same FP32 operation as in renorm, so the
+// result is identical (branch-free)
+__device__ __forceinline__ void renorm1(int &c, float &o, float e)
+{
+    const bool lo = o < 0.0f;
+    o = lo ? o + e : o;
+    c = lo ? c - 1 : c;
+    const bool hi = o >= e;
+    o = hi ? o - e : o;
+    c = hi ? c + 1 : c;
+}
+
 __device__ __forceinline__ BeadCell propose(const BeadCell &a, const Draw &d, const SysView &v)
 {
     BeadCell n{a.cx, a.cy, a.cz, a.ox + d.dx, a.oy + d.dy, a.oz + d.dz};
-    renorm(n.cx, n.ox, v.e0);
-    renorm(n.cy, n.oy, v.e1);
-    renorm(n.cz, n.oz, v.e2);
+    renorm1(n.cx, n.ox, v.e0);
+    renorm1(n.cy, n.oy, v.e1);
+    renorm1(n.cz, n.oz, v.e2);
     return n;
 }
 
@@ -193,9 +217,9 @@ __device__ __forceinline__ CellPos locate(const BeadF32 &a, const SysView &v, bo
         c.fx = c.fy = c.fz = 0.0f;
         return c;
     }
-    c.x = wrap_cell((int)c.fx, v.n0, v.inv_n0);
-    c.y = wrap_cell((int)c.fy, v.n1, v.inv_n1);
-    c.z = wrap_cell((int)c.fz, v.n2, v.inv_n2);
+    c.x = wrap_any((int)c.fx, v.n0, v.inv_n0);
+    c.y = wrap_any((int)c.fy, v.n1, v.inv_n1);
+    c.z = wrap_any((int)c.fz, v.n2, v.inv_n2);
     return c;
 }
 __device__ __forceinline__ CellPos locate(const BeadCell &a, const SysView &v, bool &bad)
@@ -206,9 +230,9 @@ __device__ __forceinline__ CellPos locate(const BeadCell &a, const SysView &v, b
         bad = true;
         return c;
     }
-    c.x = wrap_cell(a.cx, v.n0, v.inv_n0);
-    c.y = wrap_cell(a.cy, v.n1, v.inv_n1);
-    c.z = wrap_cell(a.cz, v.n2, v.inv_n2);
+    c.x = wrap_any(a.cx, v.n0, v.inv_n0);
+    c.y = wrap_any(a.cy, v.n1, v.inv_n1);
+    c.z = wrap_any(a.cz, v.n2, v.inv_n2);
     return c;
 }
 
@@ -266,6 +290,37 @@ __device__ __forceinline__ BeadCell shfl_down1(const BeadCell &a)
 {
     return BeadCell{__shfl_down(a.cx, 1), __shfl_down(a.cy, 1), __shfl_down(a.cz, 1),
                     __shfl_down(a.ox, 1), __shfl_down(a.oy, 1), __shfl_down(a.oz, 1)};
+}
+
+// Bond neighbours of a lane's bead pair: the odd bead of the lane before
+// (left) and the even bead of the lane after (right).  In block tiles a
+// wave's first and last lanes take them from the neighbouring waves through
+// LDS; every thread of the block calls these (they hold a barrier).
+template <bool BT, class Bead>
+__device__ __forceinline__ Bead left_neighbour(const Bead &b1)
+{
+    Bead l = shfl_up1(b1);
+    if constexpr (BT) {
+        __shared__ Bead edge[16];
+        const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+        if (lane == 63) edge[w] = b1;
+        __syncthreads();
+        if (lane == 0 && w > 0) l = edge[w - 1];
+    }
+    return l;
+}
+template <bool BT, class Bead>
+__device__ __forceinline__ Bead right_neighbour(const Bead &b0)
+{
+    Bead r = shfl_down1(b0);
+    if constexpr (BT) {
+        __shared__ Bead edge[16];
+        const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+        if (lane == 0) edge[w] = b0;
+        __syncthreads();
+        if (lane == 63 && w + 1 < (int)(blockDim.x >> 6)) r = edge[w + 1];
+    }
+    return r;
 }
 
 // Positions: F32 keeps coordinates in P0..P2; CELL keeps offsets in P0..P2
@@ -515,6 +570,21 @@ __device__ __forceinline__ int chain_cls(const DevSys &S, const uint8_t *cc, uin
 __device__ __forceinline__ int zcell(const CellPos &c, const BeadF32 &) { return (int)c.fz; }
 __device__ __forceinline__ int zcell(const CellPos &, const BeadCell &b) { return b.cz; }
 
+// Types of beads i (even) and i + 1, from one pattern word.
+__device__ __forceinline__ void pattern_pair(const DevSys &S, int cls, int i, int &t0, int &t1)
+{
+    const uint4 pa = *reinterpret_cast<const uint4 *>(S.pat_a);
+    const uint4 pb = *reinterpret_cast<const uint4 *>(S.pat_b);
+    const bool use_a = cls == 0;
+    const uint32_t x = use_a ? pa.x : pb.x, y = use_a ? pa.y : pb.y;
+    const uint32_t z = use_a ? pa.z : pb.z, w = use_a ? pa.w : pb.w;
+    const int k = i >> 5;
+    const uint32_t lo = (k & 1) ? y : x, hi = (k & 1) ? w : z;
+    const uint32_t word = ((k & 2) ? hi : lo) >> (i & 31);
+    t0 = (int)(word & 1u);
+    t1 = (int)((word >> 1) & 1u);
+}
+
 __device__ __forceinline__ int wave_tile(int waves_per_block, int xcd_remap)
 {
     int bid = (int)blockIdx.x;
@@ -530,6 +600,35 @@ __device__ __forceinline__ int wave_tile(int waves_per_block, int xcd_remap)
     return __builtin_amdgcn_readfirstlane(bid * waves_per_block + (int)(threadIdx.x >> 6));
 }
 
+// Block tiles: workgroup b takes tile b (the same XCD-aware remap as wave
+// tiles); a block tile packs whole chains across all waves of the block.
+__device__ __forceinline__ int block_tile(int xcd_remap)
+{
+    int bid = (int)blockIdx.x;
+    if (xcd_remap) {
+        const int nb = (int)gridDim.x;
+        const int full = nb & ~7;
+        if (bid < full) bid = (bid & 7) * (full >> 3) + (bid >> 3);
+    }
+    return __builtin_amdgcn_readfirstlane(bid);
+}
+
+// Tiling of the sweep.  Wave tiles (BT = false): a tile is G = floor(64/P)
+// whole chains on the lanes of one wave.  Block tiles (BT = true): a tile is
+// floor(64 W / P) whole chains packed over the 64 W lanes of a block, so a
+// chain may span two waves (fewer idle lanes when 64 is not a multiple of
+// P); bond neighbours across a wave boundary go through LDS.
+template <bool BT>
+__device__ __forceinline__ const Tile *tile_table(const SweepArgs &a) { return BT ? a.ptiles : a.tiles; }
+template <bool BT>
+__device__ __forceinline__ int tile_lane() { return BT ? (int)threadIdx.x : (int)(threadIdx.x & 63); }
+// chains per tile; (64 W + 1/2) / P is at least 1/(2P) from an integer
+template <bool BT>
+__device__ __forceinline__ int tile_capacity(const DevSys &S)
+{
+    return BT ? (int)(((float)blockDim.x + 0.5f) * S.inv_P) : S.G;
+}
+
 __device__ __forceinline__ SysView make_view(const DevSys &S)
 {
     SysView v;
@@ -541,7 +640,8 @@ __device__ __forceinline__ SysView make_view(const DevSys &S)
     return v;
 }
 
-__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+__device__ __forceinline__ float3 add3(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
 
 // ---------------------------------------------------------------------------
 // The sweep kernel: even pass, odd pass, density delta (and, in density
@@ -550,16 +650,16 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a
 // ---------------------------------------------------------------------------
 // Load the positions of one wave tile (lane p of chain g holds beads 2p and
 // 2p+1).
-template <class Bead>
+template <bool BT, class Bead>
 __device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0, Bead &b1)
 {
-    const Tile T = a.tiles[tile];
+    const Tile T = tile_table<BT>(a)[tile];
     const DevSys &S = a.systems[T.sys];
     const int P = S.P;
-    const int lane = (int)(threadIdx.x & 63);
+    const int lane = tile_lane<BT>();
     const int g = (int)(((float)lane + 0.5f) * S.inv_P);
     const int p = lane - g * P;
-    const int nin = min(S.G, S.n_chains - (int)T.chain0);
+    const int nin = min(tile_capacity<BT>(S), S.n_chains - (int)T.chain0);
     b0 = Bead{};
     b1 = Bead{};
     if (g < nin) {
@@ -695,12 +795,12 @@ __device__ __forceinline__ float umb_step(float coef, float2 tn, float2 to, int 
     return coef * (t ? to.y - tn.y : to.x - tn.x);
 }
 
-template <int R, int CW, int DM, bool CPL, class Bead>
+template <int R, int CW, int DM, bool CPL, bool BT, class Bead>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                            const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
                                            uint32_t *agg_vals, Bead b0, Bead b1)
 {
-    const Tile T = a.tiles[wave];
+    const Tile T = tile_table<BT>(a)[wave];
     const DevSys &S = a.systems[T.sys];
     // per-system scalars, read once at the top so that divergent code below
     // keeps them in SGPRs instead of re-reading the table
@@ -709,12 +809,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     const bool frozen = S.frozen != 0;
     const int64_t cell_off = S.cell_off;
     const int N = S.N, P = S.P;
-    const int lane = (int)(threadIdx.x & 63);
+    const int lane = tile_lane<BT>();
     // lane / P: (lane + 1/2) / P is at least 1/(2P) from an integer, far more
     // than the FP32 error of the product
     const int g = (int)(((float)lane + 0.5f) * S.inv_P);
     const int p = lane - g * P;
-    const int nin = min(S.G, S.n_chains - (int)T.chain0);
+    const int nin = min(tile_capacity<BT>(S), S.n_chains - (int)T.chain0);
     const bool active = g < nin;
     const int chain = (int)T.chain0 + (active ? g : 0);
     const int i0 = 2 * p, i1 = 2 * p + 1;
@@ -726,8 +826,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     // results do not depend on where a chain sits in memory
     const uint32_t clog = a.chain_id[S.chain_off + chain];
     const int cls = chain_cls<CPL>(S, a.chain_class, clog);
-    const int t0 = pattern_type(S, cls, i0);
-    const int t1 = pattern_type(S, cls, i1 < N ? i1 : i0);
+    int t0, t1;
+    pattern_pair(S, cls, i0, t0, t1);
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const float delta_s = S.delta * 0x1p-23f;
     const Draw d0 = move_draw((uint32_t)i0, clog, (uint32_t)s, S.sys_id, k0, k1, delta_s);
@@ -781,28 +881,27 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     }
     const float kh = S.k_half;
 
-    // even pass: bead 2p, neighbours 2p-1 (previous lane's odd bead) and 2p+1
+    // even pass: bead 2p, neighbours 2p-1 (previous lane's odd bead) and 2p+1.
+    // dE_b = (k/2) sum_j [2 d.(r - r_j) + |d|^2] = (k/2) [2 d.sum_j (r - r_j) + n_j |d|^2]
     bool acc0;
     {
-        const Bead left = shfl_up1(b1);
+        const Bead left = left_neighbour<BT>(b1);
         const float3 de = bond(n0, b0, v);
-        const float dd = dot3(de, de);
-        float dE = 0.0f;
-        if (p > 0) dE += 2.0f * dot3(de, bond(b0, left, v)) + dd;
-        if (i1 < N) dE += 2.0f * dot3(de, bond(b0, b1, v)) + dd;
-        dE = dE * kh + dw0;
+        const float3 zero = make_float3(0.0f, 0.0f, 0.0f);
+        const float3 bl = p > 0 ? bond(b0, left, v) : zero, br = i1 < N ? bond(b0, b1, v) : zero;
+        const float nj = (p > 0 ? 1.0f : 0.0f) + (i1 < N ? 1.0f : 0.0f);
+        const float dE = fmaf(fmaf(2.0f, dot3(de, add3(bl, br)), nj * dot3(de, de)), kh, dw0);
         acc0 = active && !out0 && (d0.u < __expf(-dE));
         if (acc0) b0 = n0;
     }
     // odd pass: bead 2p+1, neighbours 2p (this lane, updated) and 2p+2 (next lane)
     bool acc1;
     {
-        const Bead right = shfl_down1(b0);
+        const Bead right = right_neighbour<BT>(b0);
         const float3 de = bond(n1, b1, v);
-        const float dd = dot3(de, de);
-        float dE = 2.0f * dot3(de, bond(b1, b0, v)) + dd;
-        if (i1 + 1 < N) dE += 2.0f * dot3(de, bond(b1, right, v)) + dd;
-        dE = dE * kh + dw1;
+        const float3 br = i1 + 1 < N ? bond(b1, right, v) : make_float3(0.0f, 0.0f, 0.0f);
+        const float nj = i1 + 1 < N ? 2.0f : 1.0f;
+        const float dE = fmaf(fmaf(2.0f, dot3(de, add3(bond(b1, b0, v), br)), nj * dot3(de, de)), kh, dw1);
         acc1 = has1 && !out1 && (d1.u < __expf(-dE));
         if (acc1) b1 = n1;
     }
@@ -811,12 +910,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     // trial cells serve (and the selection costs no registers)
     const CellPos f0 = CPL ? (acc0 ? s0 : c0) : s0, f1 = CPL ? (acc1 ? s1 : c1) : s1;
     int u0 = t0, u1 = t1;
-    if (CPL && S.zones) {
+    if (CPL && !BT && S.zones) {   // (the host never packs contexts with zones)
         const int ncls = zone_convert(a, S, T.sys, clog, cls, active, p, P, has1, zcell(f0, b0), zcell(f1, b1));
-        u0 = pattern_type(S, ncls, i0);
-        u1 = pattern_type(S, ncls, i1 < N ? i1 : i0);
+        pattern_pair(S, ncls, i0, u0, u1);
     }
-    tile_finish<CW, DM>(a, wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals,
+    tile_finish<CW, DM>(a, BT ? wave * 16 + (int)(threadIdx.x >> 6) : wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals,
                         active && ((acc0 && nc0 != old0) || u0 != t0), c0, f0, t0, u0,
                         has1 && ((acc1 && nc1 != old1) || u1 != t1), c1, f1, t1, u1, acc0, acc1, active && bad);
 }
@@ -928,22 +1026,22 @@ __device__ __forceinline__ float field_step(const SweepArgs &a, bool frozen, con
 // One wave tile with smart moves.  The odd bead's proposal depends on the
 // even pass (its bond force uses the moved even beads), so the two passes
 // gather their fields one after the other.
-template <int R, int CW, int DM, bool CPL, class Bead>
+template <int R, int CW, int DM, bool CPL, bool BT, class Bead>
 __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                                const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
                                                uint32_t *agg_vals, Bead b0, Bead b1)
 {
-    const Tile T = a.tiles[wave];
+    const Tile T = tile_table<BT>(a)[wave];
     const DevSys &S = a.systems[T.sys];
     const SysView v = make_view(S);
     const FieldCoef fc{S.cAA, S.cAB, S.cBA, S.cBB, S.c0};
     const bool frozen = S.frozen != 0;
     const int64_t cell_off = S.cell_off;
     const int N = S.N, P = S.P;
-    const int lane = (int)(threadIdx.x & 63);
+    const int lane = tile_lane<BT>();
     const int g = (int)(((float)lane + 0.5f) * S.inv_P);
     const int p = lane - g * P;
-    const int nin = min(S.G, S.n_chains - (int)T.chain0);
+    const int nin = min(tile_capacity<BT>(S), S.n_chains - (int)T.chain0);
     const bool active = g < nin;
     const int chain = (int)T.chain0 + (active ? g : 0);
     const int i0 = 2 * p, i1 = 2 * p + 1;
@@ -972,7 +1070,7 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
         double xi[3];
         float u;
         smc_draw((uint32_t)i0, clog, (uint32_t)s, S.sys_id, k0, k1, xi, u);
-        const Bead left = shfl_up1(b1);
+        const Bead left = left_neighbour<BT>(b1);
         const bool hl = p > 0, hr = i1 < N;
         double3 F;
         bool inside;
@@ -999,7 +1097,7 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
         double xi[3];
         float u;
         smc_draw((uint32_t)i1, clog, (uint32_t)s, S.sys_id, k0, k1, xi, u);
-        const Bead right = shfl_down1(b0);
+        const Bead right = right_neighbour<BT>(b0);
         const bool hr = i1 + 1 < N;
         double3 F;
         bool inside;
@@ -1022,12 +1120,12 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
     // trial cells serve (and the selection costs no registers)
     const CellPos f0 = CPL ? (acc0 ? s0 : c0) : s0, f1 = CPL ? (acc1 ? s1 : c1) : s1;
     int u0 = t0, u1 = t1;
-    if (CPL && S.zones) {
+    if (CPL && !BT && S.zones) {   // (the host never packs contexts with zones)
         const int ncls = zone_convert(a, S, T.sys, clog, cls, active, p, P, has1, zcell(f0, b0), zcell(f1, b1));
         u0 = pattern_type(S, ncls, i0);
         u1 = pattern_type(S, ncls, i1 < N ? i1 : i0);
     }
-    tile_finish<CW, DM>(a, wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals,
+    tile_finish<CW, DM>(a, BT ? wave * 16 + (int)(threadIdx.x >> 6) : wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals,
                         active && ((acc0 && nc0 != old0) || u0 != t0), c0, f0, t0, u0,
                         has1 && ((acc1 && nc1 != old1) || u1 != t1), c1, f1, t1, u1, acc0, acc1, active && bad);
 }
@@ -1040,7 +1138,7 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
 // one-tile case.  With FI every thread also folds count words of the
 // previous sweep: the first word's loads are issued before the move work
 // and its stores after it, so they overlap.
-template <int R, int CW, bool LOOP, int DM, bool SMC, bool CPL>
+template <int R, int CW, bool LOOP, int DM, bool SMC, bool CPL, bool BT>
 __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 {
     using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
@@ -1054,7 +1152,7 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     const uint32_t *cin = FI ? a.base + ((s + 1) & 1) * W : a.base;
     const uint32_t *dprev = FI ? a.delta + ((s + 2) % 3) * W : nullptr;
     uint32_t *dcur = FI ? a.delta + (s % 3) * W : (DM == 2 ? a.flux + (s & 1) * 3 * W : a.delta);
-    const int wave = wave_tile(a.waves_per_block, a.xcd_remap);
+    const int wave = BT ? block_tile(a.xcd_remap) : wave_tile(a.waves_per_block, a.xcd_remap);
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // this wave's aggregation table (2 SLOTS words of dynamic LDS per wave)
     HIP_DYNAMIC_SHARED(uint32_t, agg_lds)
@@ -1073,22 +1171,24 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         const int t_end = (int)((int64_t)a.n_tiles * (wave + 1) / n_waves);
         for (int t = t_begin; t < t_end; ++t) {
             Bead b0, b1;
-            tile_load(a, t, b0, b1);
+            tile_load<false>(a, t, b0, b1);
             agg_clear<SLOTS>(agg_keys, agg_vals);
             if (SMC && a.systems[a.tiles[t].sys].smc)
-                sweep_tile_smc<R, CW, DM, CPL>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile_smc<R, CW, DM, CPL, false>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
             else
-                sweep_tile<R, CW, DM, CPL>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile<R, CW, DM, CPL, false>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
         }
     } else {
-        if (wave < a.n_tiles) {
+        // block tiles: the test is uniform over the block, so every thread
+        // of a working block reaches the barriers of the tile
+        if (wave < (BT ? a.n_ptiles : a.n_tiles)) {
             Bead b0, b1;
-            tile_load(a, wave, b0, b1);
+            tile_load<BT>(a, wave, b0, b1);
             agg_clear<SLOTS>(agg_keys, agg_vals);
-            if (SMC && a.systems[a.tiles[wave].sys].smc)
-                sweep_tile_smc<R, CW, DM, CPL>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+            if (SMC && a.systems[tile_table<BT>(a)[wave].sys].smc)
+                sweep_tile_smc<R, CW, DM, CPL, BT>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
             else
-                sweep_tile<R, CW, DM, CPL>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile<R, CW, DM, CPL, BT>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
         }
     }
     if constexpr (FI) {
@@ -1533,8 +1633,8 @@ __global__ __launch_bounds__(256) void k_init_walks(InitArgs a)
 
 // ---------------------------------------------------------------------------
 // Placement from target concentration fields (Sec. 3.2, "Coupling"): each
-// molecule is placed within half a mean end-to-end distance of a target
-// position that follows the supplied fields.
+// molecule's centre ends up at most Re/2 (half the ideal end-to-end
+// distance) from a target position drawn from the supplied fields.
 //   1. Class k (pattern a or b, A fraction f_k) weighs cell c by the integer
 //      w_k(c) = floor(2^20 (f_k tA(c) + (1 - f_k) tB(c)) + 1/2) (FP64, exact
 //      as the same operations on any IEEE machine); W_k is its exact
@@ -1856,12 +1956,16 @@ static void launch_sweep_d(const SweepArgs &a, int blocks, hipStream_t st)
     const size_t lds = sizeof(uint32_t) * 2 * (DM == 2 ? kAggSlotsFaces : kAggSlotsCells) * a.waves_per_block;
     // contexts without walls, zones, umbrella or caller-set classes launch
     // kernels built without that code (fewer registers)
+    // block tiles: one tile per block (never with conversion zones, whose
+    // chain sums stay within a wave)
     if (a.cpl) {
-        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, true>), g, b, lds, st, a);
-        else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true>), g, b, lds, st, a);
+        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, true, false>), g, b, lds, st, a);
+        else if (a.packed) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true, true>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true, false>), g, b, lds, st, a);
     } else {
-        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, false>), g, b, lds, st, a);
-        else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false>), g, b, lds, st, a);
+        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, false, false>), g, b, lds, st, a);
+        else if (a.packed) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, true>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, false>), g, b, lds, st, a);
     }
 }
 
@@ -1886,6 +1990,8 @@ hipError_t launch_sweep(int repr, int cw, const SweepArgs &a, hipStream_t st)
 {
     int blocks = (a.n_tiles + a.waves_per_block - 1) / a.waves_per_block;
     if (a.max_blocks > 0 && blocks > a.max_blocks) blocks = a.max_blocks;
+    if (a.packed && a.max_blocks == 0) blocks = a.n_ptiles;
+    if (blocks <= 0) return hipErrorInvalidConfiguration;   // the tile tables are empty
     if (repr == REPR_F32)
         return cw == COUNT_U16 ? launch_sweep_t<REPR_F32, COUNT_U16>(a, blocks, st)
                                : launch_sweep_t<REPR_F32, COUNT_U32>(a, blocks, st);

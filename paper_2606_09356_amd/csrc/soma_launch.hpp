@@ -11,6 +11,9 @@ struct SweepArgs {
     const DevSys *systems;
     const Tile *tiles;
     int n_tiles;
+    const Tile *ptiles;            // block tiles (chains packed over the waves of a block)
+    int n_ptiles;
+    int packed;                    // 1: one block tile per block (only with max_blocks == 0)
     int waves_per_block;
     int max_blocks;                // 0: one tile per wave; else the grid size (waves loop over tiles)
     int xcd_remap;

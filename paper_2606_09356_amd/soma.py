@@ -45,7 +45,7 @@ class soma_options(C.Structure):
                 ("use_graph", C.c_int32), ("density_mode", C.c_int32), ("reorder_every", C.c_int32),
                 ("waves_per_block", C.c_int32), ("waves_per_cu", C.c_int32), ("sys_id_base", C.c_int32),
                 ("launch_order", C.c_int32),
-                ("hip_stream", C.c_void_p), ("coupling", C.c_int32)]
+                ("hip_stream", C.c_void_p), ("coupling", C.c_int32), ("packed_tiles", C.c_int32)]
 
 
 class soma_obs(C.Structure):
@@ -60,13 +60,13 @@ class soma_info(C.Structure):
     _fields_ = [("n_systems", C.c_int32), ("n_tiles", C.c_int32), ("n_beads", C.c_int64),
                 ("n_cells", C.c_int64), ("sweep", C.c_uint64), ("bytes_per_sweep", C.c_int64),
                 ("density_mode", C.c_int32), ("waves_per_block", C.c_int32),
-                ("waves_per_cu", C.c_int32), ("xcd_remap", C.c_int32)]
+                ("waves_per_cu", C.c_int32), ("xcd_remap", C.c_int32), ("packed_tiles", C.c_int32)]
 
 
 class soma_tune(C.Structure):
     _fields_ = [("waves_per_block", C.c_int32), ("waves_per_cu", C.c_int32), ("xcd_remap", C.c_int32),
                 ("density_mode", C.c_int32), ("n_candidates", C.c_int32), ("us_per_sweep", C.c_double),
-                ("us_per_sweep_before", C.c_double), ("from_cache", C.c_int32)]
+                ("us_per_sweep_before", C.c_double), ("from_cache", C.c_int32), ("packed_tiles", C.c_int32)]
 
 
 class soma_ktimes(C.Structure):
@@ -159,7 +159,7 @@ class Soma:
     def __init__(self, systems: Sequence[SystemDesc], seed: int = 0, pos_repr: str = "f32",
                  count_width: int = 16, use_graph: bool = True, density_mode: int = 0,
                  reorder_every: int = 0, waves_per_block: int = 0, waves_per_cu: int = 0,
-                 sys_id_base: int = 0, launch_order: int = 0, coupling: bool = False,
+                 sys_id_base: int = 0, launch_order: int = 0, coupling: bool = False, packed_tiles: int = 0,
                  device: str = "cuda:0", stream=None):
         import torch
         self._torch = torch
@@ -181,6 +181,7 @@ class Soma:
         o.sys_id_base = sys_id_base
         o.launch_order = launch_order
         o.coupling = int(bool(coupling))
+        o.packed_tiles = int(packed_tiles)
         o.hip_stream = self.stream.cuda_stream
         self.options = o
         self.pos_repr = o.pos_repr

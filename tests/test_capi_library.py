@@ -75,8 +75,37 @@ def test_invalid_options_are_rejected(lib):
     arr, keep = S._desc_array(W.plain_small())
     n = C.c_size_t(0)
     for kw in [dict(pos_repr=3), dict(count_width=7), dict(waves_per_block=17), dict(density_mode=3),
-               dict(density_mode=-1), dict(sys_id_base=-1), dict(launch_order=2), dict(waves_per_cu=65)]:
+               dict(density_mode=-1), dict(sys_id_base=-1), dict(launch_order=2), dict(waves_per_cu=65),
+               dict(packed_tiles=2), dict(packed_tiles=1, waves_per_cu=8)]:
         assert lib.soma_workspace_size(arr, 1, C.byref(_opts(**kw)), C.byref(n)) == S.SOMA_EINVAL, kw
+
+
+@pytest.mark.parametrize("walls,zones,dm", [((0, 20), (0, 0), 0), ((5, 3), (0, 0), 0), ((-1, 8), (0, 0), 0),
+                                            ((0, 0), (2, 0), 0), ((0, 16), (9, 8), 0), ((0, 16), (2, 2), 2),
+                                            ((0, 16), (-1, 0), 0)])
+def test_invalid_walls_and_zones_are_rejected(lib, walls, zones, dm):
+    s = W.plain_small()[0]
+    s.walls, s.zones = walls, zones
+    arr, keep = S._desc_array([s])
+    n = C.c_size_t(0)
+    assert lib.soma_workspace_size(arr, 1, C.byref(_opts(density_mode=dm)), C.byref(n)) == S.SOMA_EINVAL
+
+
+def test_walls_zones_and_packed_tiles_accepted_when_valid(lib):
+    s = W.plain_small()[0]
+    s.walls, s.zones = (2, 14), (3, 3)
+    arr, keep = S._desc_array([s])
+    n = C.c_size_t(0)
+    assert lib.soma_workspace_size(arr, 1, C.byref(_opts(density_mode=1)), C.byref(n)) == 0
+    # zones exclude block tiles; without zones they are accepted
+    assert lib.soma_workspace_size(arr, 1, C.byref(_opts(packed_tiles=1)), C.byref(n)) == S.SOMA_EINVAL
+    s.zones = (0, 0)
+    arr, keep = S._desc_array([s])
+    assert lib.soma_workspace_size(arr, 1, C.byref(_opts(packed_tiles=1)), C.byref(n)) == 0
+    # the coupling workspace adds target fields (8 B/cell) and placement sums (16 B/cell)
+    m = C.c_size_t(0)
+    assert lib.soma_workspace_size(arr, 1, C.byref(_opts(coupling=1)), C.byref(m)) == 0
+    assert m.value - n.value >= 24 * s.n_cells
 
 
 def test_create_rejects_short_or_misaligned_workspace(lib):

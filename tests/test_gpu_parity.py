@@ -129,11 +129,12 @@ def test_fields_match_oracle(name):
     g.close()
 
 
-@pytest.mark.parametrize("reorder,dm", [(0, 0), (1, 0), (0, 2), (1, 1)])
+@pytest.mark.parametrize("reorder,dm,pk", [(0, 0, 0), (1, 0, 0), (0, 2, 0), (1, 1, 0), (0, 0, 1), (1, 2, 1)])
 @pytest.mark.parametrize("name", list(small_cases()))
-def test_single_and_multi_sweep_parity(name, reorder, dm):
+def test_single_and_multi_sweep_parity(name, reorder, dm, pk):
     systems, r, cw = small_cases()[name]
-    g, orcs = make_pair(systems, r, cw, reorder_every=reorder, density_mode=dm)
+    g, orcs = make_pair(systems, r, cw, reorder_every=reorder, density_mode=dm, packed_tiles=pk,
+                        waves_per_block=3 if pk else 0)
     total, mism = 0, 0
     for sweep in range(3):
         g.sweep(1)
@@ -204,14 +205,18 @@ def test_gpu_init_matches_oracle_walks(r):
 def test_graph_tiling_and_xcd_invariance():
     systems = W.batched_mixed(n_systems=6, seed=46, bead_range=(2000, 15000))
     ref = None
-    for use_graph, wpb, wpcu, reorder, dm in [(False, 1, 0, 0, 0), (True, 4, 0, 0, 0), (True, 16, 0, 0, 0),
-                                              (False, 7, 0, 0, 0), (True, 4, 1, 0, 0), (True, 2, 8, 0, 0),
-                                              (True, 4, 0, 1, 0), (False, 4, 0, 2, 0), (True, 4, 0, 3, 0),
-                                              (True, 4, 0, 0, 1), (False, 1, 0, 2, 1), (True, 2, 8, 3, 1),
-                                              (True, 16, 32, 0, 1), (True, 4, 0, 0, 2), (False, 1, 0, 2, 2),
-                                              (True, 2, 8, 3, 2), (True, 16, 32, 0, 2)]:
+    for use_graph, wpb, wpcu, reorder, dm, pk in [
+            (False, 1, 0, 0, 0, 0), (True, 4, 0, 0, 0, 0), (True, 16, 0, 0, 0, 0),
+            (False, 7, 0, 0, 0, 0), (True, 4, 1, 0, 0, 0), (True, 2, 8, 0, 0, 0),
+            (True, 4, 0, 1, 0, 0), (False, 4, 0, 2, 0, 0), (True, 4, 0, 3, 0, 0),
+            (True, 4, 0, 0, 1, 0), (False, 1, 0, 2, 1, 0), (True, 2, 8, 3, 1, 0),
+            (True, 16, 32, 0, 1, 0), (True, 4, 0, 0, 2, 0), (False, 1, 0, 2, 2, 0),
+            (True, 2, 8, 3, 2, 0), (True, 16, 32, 0, 2, 0),
+            # block tiles: chains packed over the waves of a workgroup
+            (True, 2, 0, 0, 0, 1), (False, 4, 0, 2, 0, 1), (True, 16, 0, 0, 1, 1), (True, 3, 0, 1, 2, 1),
+            (True, 8, 0, 0, 2, 1)]:
         g = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, use_graph=use_graph, waves_per_block=wpb,
-                 waves_per_cu=wpcu, reorder_every=reorder, density_mode=dm)
+                 waves_per_cu=wpcu, reorder_every=reorder, density_mode=dm, packed_tiles=pk)
         g.sweep(2)
         g.sweep(3)
         st = [g.state(k) for k in range(len(systems))]
@@ -220,8 +225,8 @@ def test_graph_tiling_and_xcd_invariance():
             ref, ref_den = st, den
         else:
             for a, b, da, db in zip(ref, st, ref_den, den):
-                assert (a[0] == b[0]).all() and (a[1] == b[1]).all(), (use_graph, wpb, wpcu, reorder, dm)
-                assert (da == db).all(), (use_graph, wpb, wpcu, reorder, dm)
+                assert (a[0] == b[0]).all() and (a[1] == b[1]).all(), (use_graph, wpb, wpcu, reorder, dm, pk)
+                assert (da == db).all(), (use_graph, wpb, wpcu, reorder, dm, pk)
         g.close()
 
 
@@ -243,18 +248,18 @@ def test_autotune_keeps_the_trajectory(r):
     b.sweep(2)
     t = a.autotune(trial_sweeps=2)
     print(f"[autotune {r}] {t}", flush=True)
-    assert t["n_candidates"] == 90 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
+    assert t["n_candidates"] == 114 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
     i = a.info()
-    assert (i["waves_per_block"], i["waves_per_cu"], i["xcd_remap"], i["density_mode"]) == \
-        (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"], t["density_mode"])
+    assert (i["waves_per_block"], i["waves_per_cu"], i["xcd_remap"], i["density_mode"], i["packed_tiles"]) == \
+        (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"], t["density_mode"], t["packed_tiles"])
     assert i["sweep"] == 2
     # a second context with the same key takes the cached shape without timing
     c = Soma(systems, seed=SEED, pos_repr=r, count_width=16, reorder_every=3)
     tc = c.autotune(trial_sweeps=2)
     assert tc["from_cache"] == 1 and tc["n_candidates"] == 0
     ic = c.info()
-    assert (ic["waves_per_block"], ic["waves_per_cu"], ic["xcd_remap"], ic["density_mode"]) == \
-        (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"], t["density_mode"])
+    assert (ic["waves_per_block"], ic["waves_per_cu"], ic["xcd_remap"], ic["density_mode"], ic["packed_tiles"]) == \
+        (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"], t["density_mode"], t["packed_tiles"])
     c.sweep(2)
     c.sweep(5)
     a.sweep(5)

@@ -31,12 +31,14 @@ def mixed_batch(seed):
     return systems
 
 
-@pytest.mark.parametrize("r,cw,dm", [("f32", 16, 0), ("f32", 16, 1), ("f32", 16, 2), ("cell", 32, 0), ("cell", 16, 1),
-                                     ("cell", 16, 2), ("cell", 32, 2)])
-def test_smart_move_parity(r, cw, dm):
+@pytest.mark.parametrize("r,cw,dm,pk", [("f32", 16, 0, 0), ("f32", 16, 1, 0), ("f32", 16, 2, 0), ("cell", 32, 0, 0),
+                                        ("cell", 16, 1, 0), ("cell", 16, 2, 0), ("cell", 32, 2, 0), ("f32", 16, 0, 1),
+                                        ("cell", 16, 2, 1)])
+def test_smart_move_parity(r, cw, dm, pk):
     systems = mixed_batch(61)
-    print(f"[smc parity] {r}/u{cw}/mode {dm}: {sum(s.n_beads for s in systems)} beads", flush=True)
-    g = Soma(systems, seed=SEED, pos_repr=r, count_width=cw, density_mode=dm, reorder_every=2)
+    print(f"[smc parity] {r}/u{cw}/mode {dm}/packed {pk}: {sum(s.n_beads for s in systems)} beads", flush=True)
+    g = Soma(systems, seed=SEED, pos_repr=r, count_width=cw, density_mode=dm, reorder_every=2, packed_tiles=pk,
+             waves_per_block=5 if pk else 0)
     mode = oracle.MODE_F32 if r == "f32" else oracle.MODE_CELL
     orcs = []
     for k, s in enumerate(systems):
