@@ -345,6 +345,27 @@ __device__ __forceinline__ void store_pair(const PosArrays &A, int64_t slot, con
     *reinterpret_cast<float2 *>(A.P1 + slot) = make_float2(a.y, b.y);
     *reinterpret_cast<float2 *>(A.P2 + slot) = make_float2(a.z, b.z);
 }
+// Store what a sweep changed: nothing for a pair whose two moves were
+// rejected; in cell mode, each cell word only when a bead of the pair left
+// its cell along that axis (a few percent of the beads), so most cell
+// sectors are never written back.
+__device__ __forceinline__ void store_moved(const PosArrays &A, int64_t slot, const BeadF32 &a, const BeadF32 &b,
+                                            const BeadF32 &, const BeadF32 &, bool moved)
+{
+    if (moved) store_pair(A, slot, a, b);
+}
+__device__ __forceinline__ void store_moved(const PosArrays &A, int64_t slot, const BeadCell &a, const BeadCell &b,
+                                            const BeadCell &oa, const BeadCell &ob, bool moved)
+{
+    if (!moved) return;
+    if (a.cx != oa.cx || b.cx != ob.cx) *reinterpret_cast<int2 *>(A.C0 + slot) = make_int2(a.cx, b.cx);
+    if (a.cy != oa.cy || b.cy != ob.cy) *reinterpret_cast<int2 *>(A.C1 + slot) = make_int2(a.cy, b.cy);
+    if (a.cz != oa.cz || b.cz != ob.cz) *reinterpret_cast<int2 *>(A.C2 + slot) = make_int2(a.cz, b.cz);
+    *reinterpret_cast<float2 *>(A.P0 + slot) = make_float2(a.ox, b.ox);
+    *reinterpret_cast<float2 *>(A.P1 + slot) = make_float2(a.oy, b.oy);
+    *reinterpret_cast<float2 *>(A.P2 + slot) = make_float2(a.oz, b.oz);
+}
+
 __device__ __forceinline__ void load_pair(const PosArrays &A, int64_t slot, BeadCell &a, BeadCell &b)
 {
     const int2 cx = *reinterpret_cast<const int2 *>(A.C0 + slot);
@@ -821,6 +842,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     const bool has1 = active && i1 < N;
     const int64_t slot = S.slot_off + (int64_t)chain * (2 * P) + i0;
     const PosArrays A{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2};
+    const Bead ob0 = b0, ob1 = b1;   // the stored state, to write back only what changes
 
     // logical chain id: keys the random numbers and picks the species, so
     // results do not depend on where a chain sits in memory
@@ -905,7 +927,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
         acc1 = has1 && !out1 && (d1.u < __expf(-dE));
         if (acc1) b1 = n1;
     }
-    if (active) store_pair(A, slot, b0, b1);
+    if (active) store_moved(A, slot, b0, b1, ob0, ob1, acc0 || acc1);
     // final cells: without coupling a change implies an accepted move, so the
     // trial cells serve (and the selection costs no registers)
     const CellPos f0 = CPL ? (acc0 ? s0 : c0) : s0, f1 = CPL ? (acc1 ? s1 : c1) : s1;
@@ -1048,6 +1070,7 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
     const bool has1 = active && i1 < N;
     const int64_t slot = S.slot_off + (int64_t)chain * (2 * P) + i0;
     const PosArrays A{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2};
+    const Bead ob0 = b0, ob1 = b1;   // the stored state, to write back only what changes
     const uint32_t clog = a.chain_id[S.chain_off + chain];
     const int cls = chain_cls<CPL>(S, a.chain_class, clog);
     const int t0 = pattern_type(S, cls, i0);
@@ -1115,7 +1138,7 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
         acc1 = has1 && inside && (u < __expf(-dE));
         if (acc1) b1 = n1;
     }
-    if (active) store_pair(A, slot, b0, b1);
+    if (active) store_moved(A, slot, b0, b1, ob0, ob1, acc0 || acc1);
     // final cells: without coupling a change implies an accepted move, so the
     // trial cells serve (and the selection costs no registers)
     const CellPos f0 = CPL ? (acc0 ? s0 : c0) : s0, f1 = CPL ? (acc1 ? s1 : c1) : s1;
