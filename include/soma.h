@@ -123,16 +123,22 @@ typedef struct {
     int32_t pos_repr;          /* SOMA_POS_* */
     int32_t count_width;       /* SOMA_COUNT_* */
     int32_t use_graph;         /* nonzero: soma_mc_sweep replays a captured hipGraph per sweep count */
-    int32_t density_mode;      /* how accepted cell changes reach the counts (always through
-                                  a per-sweep delta, merged per wave, by device atomics):
-                                  0: -1/+1 on the old and new cell's words, folded into the
-                                     counts by a streaming kernel after each sweep;
+    int32_t density_mode;      /* how accepted cell changes reach the counts (merged per
+                                  wave, then device atomics):
+                                  0: -1/+1 on the old and new cell's words of a delta buffer,
+                                     folded into the counts by a streaming kernel after each
+                                     sweep;
                                   1: the same words, folded inside the next sweep's kernel,
                                      whose gathers then read base + previous delta (two base,
                                      three delta buffers);
                                   2: face fluxes (one word per crossed cell face, so a
                                      one-axis move costs one atomic instead of two), folded
-                                     by a kernel that adds each cell's flux divergence */
+                                     by a kernel that adds each cell's flux divergence;
+                                  3: mirrored counts: a sweep gathers one of two identical
+                                     count buffers and adds its -1/+1 words straight into the
+                                     other, then a copy kernel makes them equal again (half
+                                     the upkeep traffic of mode 0; packed 16-bit overflow is
+                                     caught by an exact check of the total bead count) */
     int32_t reorder_every;     /* >0: spatially sort chains every this many sweeps; 0: never */
     int32_t waves_per_block;   /* 1..16 waves per workgroup; 0: library default */
     int32_t waves_per_cu;      /* >0: sweep grid of this many waves per compute unit, each wave

@@ -52,10 +52,11 @@ double *scratch_for_device(int dev)
 }
 
 struct Layout {
+    size_t mirror_part = 0;
     size_t systems, tiles, chain_id, chain_id2, P[3], C[3], Q[3], D[3], keys, hist, bsum, perm, base, delta, flux, chunks,
         omega, accept, status, partials, obs_out, staging, chain_class, chain_class2, conv, tgt, place_W, place_bsum,
         ptiles, total;   // base: counts, delta: density delta; ptiles: block tiles
-    int64_t total_slots = 0, total_cells = 0, total_chains = 0, count_words = 0;
+    int64_t total_slots = 0, total_cells = 0, total_chains = 0, count_words = 0, total_beads = 0;
     int n_tiles = 0;
     int n_chunks = 0;      // fold chunks of density mode 2
     int64_t max_obs_blocks = 0, max_cells = 0;
@@ -104,6 +105,10 @@ struct soma_ctx {
     // parity still holds fluxes; the other one is clear for sweep flux_sweep
     bool flux_dirty = false;
     uint64_t flux_sweep = 0;
+    // density mode 3: base[1] holds the same counts as base[0] (set when
+    // mode-3 sweeps begin, kept by them, dropped by anything else that
+    // writes the counts)
+    bool mirror = false;
     int any_smc = 0;       // some system moves with bond-force-biased moves
     int any_zones = 0;     // some system has conversion zones (density mode 2 excluded)
     uint64_t sweep = 0;
@@ -137,6 +142,8 @@ struct soma_ctx {
     unsigned long long *accept() const { return reinterpret_cast<unsigned long long *>(ws + L.accept); }
     uint32_t *status() const { return reinterpret_cast<uint32_t *>(ws + L.status); }
     uint64_t *sweep_ctr() const { return reinterpret_cast<uint64_t *>(ws + L.status + 8); }
+    // density mode 3: the copy blocks' sums of the count halves
+    unsigned long long *mirror_part() const { return reinterpret_cast<unsigned long long *>(ws + L.mirror_part); }
     double *partials() const { return reinterpret_cast<double *>(ws + L.partials); }
     double *obs_out() const { return reinterpret_cast<double *>(ws + L.obs_out); }
     void *staging() const { return ws + L.staging; }
@@ -182,7 +189,7 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
     if (opt->count_width != SOMA_COUNT_U16 && opt->count_width != SOMA_COUNT_U32) { msg = "bad count_width"; return SOMA_EINVAL; }
     if (opt->waves_per_block < 0 || opt->waves_per_block > 16) { msg = "waves_per_block must be 0..16"; return SOMA_EINVAL; }
     if (opt->waves_per_cu < 0 || opt->waves_per_cu > 64) { msg = "waves_per_cu must be 0..64"; return SOMA_EINVAL; }
-    if (opt->density_mode < 0 || opt->density_mode > 2) { msg = "density_mode must be 0, 1 or 2"; return SOMA_EINVAL; }
+    if (opt->density_mode < 0 || opt->density_mode > 3) { msg = "density_mode must be 0, 1, 2 or 3"; return SOMA_EINVAL; }
     if (opt->reorder_every < 0) { msg = "reorder_every must be >= 0"; return SOMA_EINVAL; }
     if (opt->launch_order != 0 && opt->launch_order != 1) { msg = "launch_order must be 0 or 1"; return SOMA_EINVAL; }
     if (opt->packed_tiles != 0 && opt->packed_tiles != 1) { msg = "packed_tiles must be 0 or 1"; return SOMA_EINVAL; }
@@ -246,7 +253,7 @@ void set_field_coefs(HostSys &h);
 Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt, std::vector<HostSys> *out)
 {
     Layout L{};
-    int64_t slots = 0, cells = 0, chains = 0;
+    int64_t slots = 0, cells = 0, chains = 0, beads = 0;
     int tiles = 0;
     int64_t max_blocks = 1, max_cells = 1;
     for (int32_t k = 0; k < n_sys; ++k) {
@@ -319,6 +326,7 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
         slots = align64(slots + (int64_t)d.n_chains * 2 * P);
         cells = align64(cells + M);
         chains += d.n_chains;
+        beads += (int64_t)d.n_chains * d.N;
         tiles += nt;
         max_blocks = std::max<int64_t>(max_blocks, (d.n_chains + 255) / 256 + (M + 255) / 256);
         max_cells = std::max<int64_t>(max_cells, M);
@@ -327,6 +335,7 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     L.total_slots = slots;
     L.total_cells = cells;
     L.total_chains = chains;
+    L.total_beads = beads;
     L.n_tiles = tiles;
     L.count_words = cells * (opt->count_width == SOMA_COUNT_U16 ? 1 : 2);
     L.max_obs_blocks = max_blocks;
@@ -362,6 +371,7 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     L.omega = take(sizeof(float) * 2 * cells);
     L.accept = take(sizeof(uint64_t) * soma::kAcceptSlots * soma::kAcceptStride * n_sys);
     L.status = take(64);
+    L.mirror_part = take(sizeof(unsigned long long) * soma::kMirrorBlocks);
     L.partials = take(sizeof(double) * 12 * max_blocks);
     L.obs_out = take(sizeof(double) * 8);
     L.staging = take(sizeof(float) * 2 * max_cells);
@@ -527,6 +537,7 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
 int canonicalize(soma_ctx *c)
 {
     if (!c->rot) return SOMA_OK;
+    c->mirror = false;
     const uint64_t s = c->sweep;
     HIPCHK(c, soma::launch_fold(c->cw, c->base((int)((s + 1) & 1)), c->delta((int)((s + 2) % 3)), c->base(0),
                                 c->L.count_words, c->status(), c->stream));
@@ -541,6 +552,7 @@ int canonicalize(soma_ctx *c)
 int enter_rotation(soma_ctx *c)
 {
     if (c->rot) return SOMA_OK;
+    c->mirror = false;
     const int k = (int)((c->sweep + 1) & 1);
     if (k != 0)
         HIPCHK(c, hipMemcpyAsync(c->base(k), c->base(0), sizeof(uint32_t) * c->L.count_words,
@@ -557,6 +569,12 @@ int sweep_layout(soma_ctx *c)
     if (c->density_mode == 1) return enter_rotation(c);
     int rc = canonicalize(c);
     if (rc != SOMA_OK) return rc;
+    if (c->density_mode == 3 && !c->mirror) {
+        HIPCHK(c, hipMemcpyAsync(c->base(1), c->base(0), sizeof(uint32_t) * c->L.count_words,
+                                 hipMemcpyDeviceToDevice, c->stream));
+        c->mirror = true;
+    }
+    if (c->density_mode != 3) c->mirror = false;
     if (c->density_mode == 2 && c->flux_dirty && c->sweep != c->flux_sweep) {
         HIPCHK(c, soma::launch_fill_u32(c->flux(), 6 * c->L.count_words, 0u, c->stream));
         c->flux_dirty = false;
@@ -570,6 +588,7 @@ int rebuild_density(soma_ctx *c, int32_t sys)
 {
     int rc = canonicalize(c);
     if (rc != SOMA_OK) return rc;
+    c->mirror = false;
     uint32_t *cur = c->counts();
     const int64_t wpc = c->words_per_cell();
     int tb = 0, te = c->L.n_tiles;
@@ -740,6 +759,17 @@ int record_sweeps(soma_ctx *c, int32_t n, hipStream_t st, hipEvent_t *ev = nullp
             f.rel = (uint32_t)r;
             f.status = c->status();
             HIPCHK(c, soma::launch_fold_faces(c->cw, f, c->L.n_chunks, st));
+        }
+        if (c->density_mode == 3) {
+            soma::MirrorArgs m{};
+            m.base = c->base(0);
+            m.count_words = c->L.count_words;
+            m.sweep_ctr = c->sweep_ctr();
+            m.rel = (uint32_t)r;
+            m.part = c->mirror_part();
+            m.beads = (unsigned long long)c->L.total_beads;
+            m.status = c->status();
+            HIPCHK(c, soma::launch_mirror(c->cw, m, st));
         }
         if (ev) HIPCHK(c, hipEventRecord(ev[3 * r + 2], st));
     }
@@ -1475,11 +1505,14 @@ int soma_get_info(soma_ctx *c, soma_info *out)
     out->n_beads = beads;
     out->n_cells = cells;
     out->sweep = c->sweep;
-    // positions read + write; fold of the counts: counts and delta read,
-    // counts written, delta cleared (the field gathers hit these same lines)
+    // positions read + write; the counts' upkeep: with a delta buffer (modes
+    // 0, 1) the counts and the delta read, the counts written and the delta
+    // cleared, with mirrored counts (mode 3) one copy (read and write); the
+    // field gathers hit these same lines.  (Mode 2 moves the counts and three
+    // flux arrays; it is priced like mode 0 here.)
     const int64_t pos = c->repr == soma::REPR_F32 ? 12 : 24;
     const int64_t cnt = c->cw == soma::COUNT_U16 ? 4 : 8;
-    out->bytes_per_sweep = 2 * pos * beads + 4 * cnt * cells;
+    out->bytes_per_sweep = 2 * pos * beads + (c->density_mode == 3 ? 2 : 4) * cnt * cells;
     out->density_mode = c->density_mode;
     out->waves_per_block = c->waves_per_block;
     out->waves_per_cu = c->waves_per_cu;
@@ -1605,7 +1638,7 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
     best.us_per_sweep = best.us_per_sweep_before;
     // wave tiles: one per wave, or resident grids of 8 or 32 waves per CU;
     // block tiles (-1 here): one per block
-    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32, -1}, kXcd[] = {1, 0}, kDm[] = {0, 1, 2};
+    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32, -1}, kXcd[] = {1, 0}, kDm[] = {0, 1, 2, 3};
     for (int dm : kDm)
         for (int wpb : kWpb)
             for (int wpcu : kWpcu)

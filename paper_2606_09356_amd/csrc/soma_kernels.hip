@@ -94,21 +94,17 @@ __device__ __forceinline__ int wrap_cell(int i, int n, float inv_n)
     return r;
 }
 
-// Wrap of i in [-n, 2n) into [0, n).
+// Wrap of i in [-n, 2n) into [0, n): exactly one of i, i + n, i - n lies in
+// [0, n), and read as unsigned it is the smallest of the three (the others
+// are >= n or negative).  For i outside [-n, 2n) all three are >= n, so the
+// result is >= n exactly when i was out of that range.
 __device__ __forceinline__ int wrap_step(int i, int n)
 {
-    i = i < 0 ? i + n : i;
-    return i >= n ? i - n : i;
+    const uint32_t u = (uint32_t)i, m = (uint32_t)n;
+    return (int)min(min(u, u + m), u - m);
 }
 
-// Wrap of any unwrapped index: beads are almost always within one image of
-// the box, where two compares suffice; the general form runs only for the
-// lanes that need it.
-__device__ __forceinline__ int wrap_any(int i, int n, float inv_n)
-{
-    if (i >= -n && i < 2 * n) return wrap_step(i, n);
-    return wrap_cell(i, n, inv_n);
-}
+__device__ __forceinline__ bool wrapped(int w, int n) { return (uint32_t)w < (uint32_t)n; }
 
 // ---------------------------------------------------------------------------
 // Position representations
@@ -204,6 +200,9 @@ struct CellPos {
     float fx, fy, fz;
 };
 
+// Beads almost always lie within one image of the box, where wrap_step is
+// the wrap; the general form (and the range check) runs only for the lanes
+// that need it.
 __device__ __forceinline__ CellPos locate(const BeadF32 &a, const SysView &v, bool &bad)
 {
     CellPos c;
@@ -211,35 +210,45 @@ __device__ __forceinline__ CellPos locate(const BeadF32 &a, const SysView &v, bo
     c.fy = floor_div(a.y, v.e1, v.ie1, v.dyadic);
     c.fz = floor_div(a.z, v.e2, v.ie2, v.dyadic);
     const float lim = (float)kCellLimit;
-    if (!(fabsf(c.fx) < lim && fabsf(c.fy) < lim && fabsf(c.fz) < lim)) {
-        bad = true;
-        c.x = c.y = c.z = 0;
-        c.fx = c.fy = c.fz = 0.0f;
-        return c;
+    c.x = wrap_step((int)c.fx, v.n0);
+    c.y = wrap_step((int)c.fy, v.n1);
+    c.z = wrap_step((int)c.fz, v.n2);
+    // (a non-finite coordinate fails the magnitude test)
+    if (!(wrapped(c.x, v.n0) && wrapped(c.y, v.n1) && wrapped(c.z, v.n2) && fabsf(c.fx) < lim &&
+          fabsf(c.fy) < lim && fabsf(c.fz) < lim)) {
+        if (!(fabsf(c.fx) < lim && fabsf(c.fy) < lim && fabsf(c.fz) < lim)) {
+            bad = true;
+            c.x = c.y = c.z = 0;
+            c.fx = c.fy = c.fz = 0.0f;
+            return c;
+        }
+        c.x = wrap_cell((int)c.fx, v.n0, v.inv_n0);
+        c.y = wrap_cell((int)c.fy, v.n1, v.inv_n1);
+        c.z = wrap_cell((int)c.fz, v.n2, v.inv_n2);
     }
-    c.x = wrap_any((int)c.fx, v.n0, v.inv_n0);
-    c.y = wrap_any((int)c.fy, v.n1, v.inv_n1);
-    c.z = wrap_any((int)c.fz, v.n2, v.inv_n2);
     return c;
 }
 __device__ __forceinline__ CellPos locate(const BeadCell &a, const SysView &v, bool &bad)
 {
-    CellPos c{0, 0, 0, 0.0f, 0.0f, 0.0f};
-    if (a.cx <= -kCellLimit || a.cx >= kCellLimit || a.cy <= -kCellLimit || a.cy >= kCellLimit ||
-        a.cz <= -kCellLimit || a.cz >= kCellLimit) {
-        bad = true;
-        return c;
+    CellPos c{wrap_step(a.cx, v.n0), wrap_step(a.cy, v.n1), wrap_step(a.cz, v.n2), 0.0f, 0.0f, 0.0f};
+    if (!(wrapped(c.x, v.n0) && wrapped(c.y, v.n1) && wrapped(c.z, v.n2))) {
+        if (a.cx <= -kCellLimit || a.cx >= kCellLimit || a.cy <= -kCellLimit || a.cy >= kCellLimit ||
+            a.cz <= -kCellLimit || a.cz >= kCellLimit) {
+            bad = true;
+            c.x = c.y = c.z = 0;
+            return c;
+        }
+        c.x = wrap_cell(a.cx, v.n0, v.inv_n0);
+        c.y = wrap_cell(a.cy, v.n1, v.inv_n1);
+        c.z = wrap_cell(a.cz, v.n2, v.inv_n2);
     }
-    c.x = wrap_any(a.cx, v.n0, v.inv_n0);
-    c.y = wrap_any(a.cy, v.n1, v.inv_n1);
-    c.z = wrap_any(a.cz, v.n2, v.inv_n2);
     return c;
 }
 
 // Cell of a trial position.  The move half-width is below 0.99 cell edges,
 // so the unwrapped index changes by at most one per axis (clamped so that a
 // non-finite coordinate still yields an in-range cell).
-__device__ __forceinline__ int clamp1(int k) { return k < -1 ? -1 : (k > 1 ? 1 : k); }
+__device__ __forceinline__ int clamp1(int k) { return max(-1, min(k, 1)); }
 
 __device__ __forceinline__ CellPos step(const CellPos &o, const BeadF32 &, const BeadF32 &n, const SysView &v)
 {
@@ -254,10 +263,12 @@ __device__ __forceinline__ CellPos step(const CellPos &o, const BeadF32 &, const
 }
 __device__ __forceinline__ CellPos step(const CellPos &o, const BeadCell &ob, const BeadCell &n, const SysView &v)
 {
+    // (a trial offset renormalises by at most one cell per axis, so the
+    // stored cells differ by -1, 0 or 1)
     CellPos c{0, 0, 0, 0.0f, 0.0f, 0.0f};
-    c.x = wrap_step(o.x + clamp1(n.cx - ob.cx), v.n0);
-    c.y = wrap_step(o.y + clamp1(n.cy - ob.cy), v.n1);
-    c.z = wrap_step(o.z + clamp1(n.cz - ob.cz), v.n2);
+    c.x = wrap_step(o.x + (n.cx - ob.cx), v.n0);
+    c.y = wrap_step(o.y + (n.cy - ob.cy), v.n1);
+    c.z = wrap_step(o.z + (n.cz - ob.cz), v.n2);
     return c;
 }
 
@@ -330,20 +341,30 @@ struct PosArrays {
     int *C0, *C1, *C2;
 };
 
+// Position lines stay in the caches between a wave's loads and its stores:
+// most stored lines are partial (only changed pairs are written back) and are
+// completed in the L2 from the loaded data before they reach memory.
+// (Non-temporal loads or stores, which keep lines out of the caches, made the
+// sweep slower.)
+__device__ __forceinline__ float2 ld2(const float *p) { return *reinterpret_cast<const float2 *>(p); }
+__device__ __forceinline__ int2 ld2(const int *p) { return *reinterpret_cast<const int2 *>(p); }
+__device__ __forceinline__ void st2(float *p, float x, float y) { *reinterpret_cast<float2 *>(p) = make_float2(x, y); }
+__device__ __forceinline__ void st2(int *p, int x, int y) { *reinterpret_cast<int2 *>(p) = make_int2(x, y); }
+
 __device__ __forceinline__ void load_pair(const PosArrays &A, int64_t slot, BeadF32 &a, BeadF32 &b)
 {
-    const float2 x = *reinterpret_cast<const float2 *>(A.P0 + slot);
-    const float2 y = *reinterpret_cast<const float2 *>(A.P1 + slot);
-    const float2 z = *reinterpret_cast<const float2 *>(A.P2 + slot);
+    const float2 x = ld2(A.P0 + slot);
+    const float2 y = ld2(A.P1 + slot);
+    const float2 z = ld2(A.P2 + slot);
     a = BeadF32{x.x, y.x, z.x};
     b = BeadF32{x.y, y.y, z.y};
 }
 __device__ __forceinline__ void store_pair(const PosArrays &A, int64_t slot, const BeadF32 &a,
                                            const BeadF32 &b)
 {
-    *reinterpret_cast<float2 *>(A.P0 + slot) = make_float2(a.x, b.x);
-    *reinterpret_cast<float2 *>(A.P1 + slot) = make_float2(a.y, b.y);
-    *reinterpret_cast<float2 *>(A.P2 + slot) = make_float2(a.z, b.z);
+    st2(A.P0 + slot, a.x, b.x);
+    st2(A.P1 + slot, a.y, b.y);
+    st2(A.P2 + slot, a.z, b.z);
 }
 // Store what a sweep changed: nothing for a pair whose two moves were
 // rejected; in cell mode, each cell word only when a bead of the pair left
@@ -358,34 +379,34 @@ __device__ __forceinline__ void store_moved(const PosArrays &A, int64_t slot, co
                                             const BeadCell &oa, const BeadCell &ob, bool moved)
 {
     if (!moved) return;
-    if (a.cx != oa.cx || b.cx != ob.cx) *reinterpret_cast<int2 *>(A.C0 + slot) = make_int2(a.cx, b.cx);
-    if (a.cy != oa.cy || b.cy != ob.cy) *reinterpret_cast<int2 *>(A.C1 + slot) = make_int2(a.cy, b.cy);
-    if (a.cz != oa.cz || b.cz != ob.cz) *reinterpret_cast<int2 *>(A.C2 + slot) = make_int2(a.cz, b.cz);
-    *reinterpret_cast<float2 *>(A.P0 + slot) = make_float2(a.ox, b.ox);
-    *reinterpret_cast<float2 *>(A.P1 + slot) = make_float2(a.oy, b.oy);
-    *reinterpret_cast<float2 *>(A.P2 + slot) = make_float2(a.oz, b.oz);
+    if (a.cx != oa.cx || b.cx != ob.cx) st2(A.C0 + slot, a.cx, b.cx);
+    if (a.cy != oa.cy || b.cy != ob.cy) st2(A.C1 + slot, a.cy, b.cy);
+    if (a.cz != oa.cz || b.cz != ob.cz) st2(A.C2 + slot, a.cz, b.cz);
+    st2(A.P0 + slot, a.ox, b.ox);
+    st2(A.P1 + slot, a.oy, b.oy);
+    st2(A.P2 + slot, a.oz, b.oz);
 }
 
 __device__ __forceinline__ void load_pair(const PosArrays &A, int64_t slot, BeadCell &a, BeadCell &b)
 {
-    const int2 cx = *reinterpret_cast<const int2 *>(A.C0 + slot);
-    const int2 cy = *reinterpret_cast<const int2 *>(A.C1 + slot);
-    const int2 cz = *reinterpret_cast<const int2 *>(A.C2 + slot);
-    const float2 x = *reinterpret_cast<const float2 *>(A.P0 + slot);
-    const float2 y = *reinterpret_cast<const float2 *>(A.P1 + slot);
-    const float2 z = *reinterpret_cast<const float2 *>(A.P2 + slot);
+    const int2 cx = ld2(A.C0 + slot);
+    const int2 cy = ld2(A.C1 + slot);
+    const int2 cz = ld2(A.C2 + slot);
+    const float2 x = ld2(A.P0 + slot);
+    const float2 y = ld2(A.P1 + slot);
+    const float2 z = ld2(A.P2 + slot);
     a = BeadCell{cx.x, cy.x, cz.x, x.x, y.x, z.x};
     b = BeadCell{cx.y, cy.y, cz.y, x.y, y.y, z.y};
 }
 __device__ __forceinline__ void store_pair(const PosArrays &A, int64_t slot, const BeadCell &a,
                                            const BeadCell &b)
 {
-    *reinterpret_cast<int2 *>(A.C0 + slot) = make_int2(a.cx, b.cx);
-    *reinterpret_cast<int2 *>(A.C1 + slot) = make_int2(a.cy, b.cy);
-    *reinterpret_cast<int2 *>(A.C2 + slot) = make_int2(a.cz, b.cz);
-    *reinterpret_cast<float2 *>(A.P0 + slot) = make_float2(a.ox, b.ox);
-    *reinterpret_cast<float2 *>(A.P1 + slot) = make_float2(a.oy, b.oy);
-    *reinterpret_cast<float2 *>(A.P2 + slot) = make_float2(a.oz, b.oz);
+    st2(A.C0 + slot, a.cx, b.cx);
+    st2(A.C1 + slot, a.cy, b.cy);
+    st2(A.C2 + slot, a.cz, b.cz);
+    st2(A.P0 + slot, a.ox, b.ox);
+    st2(A.P1 + slot, a.oy, b.oy);
+    st2(A.P2 + slot, a.oz, b.oz);
 }
 
 // ---------------------------------------------------------------------------
@@ -456,10 +477,15 @@ __device__ __forceinline__ uint2 counts_of(const RawCount &r)
 constexpr int kAggSlotsCells = 256;
 constexpr int kAggSlotsFaces = 512;
 
+// Multiplicative hash of the low 24 bits of the key.  The product is taken
+// with the full-rate 24-bit multiply (left to itself the compiler narrows the
+// constant and emits the quarter-rate 32-bit multiply).
 template <int SLOTS>
 __device__ __forceinline__ uint32_t agg_hash(uint32_t key)
 {
-    return (__umul24(key, 0x9E3779u) >> 10) & (SLOTS - 1);
+    uint32_t p;
+    asm("v_mul_u32_u24 %0, 0x9e3779, %1" : "=v"(p) : "v"(key));
+    return (p >> 10) & (SLOTS - 1);
 }
 
 template <int SLOTS>
@@ -672,7 +698,7 @@ __device__ __forceinline__ float3 add3(float3 a, float3 b) { return make_float3(
 // Load the positions of one wave tile (lane p of chain g holds beads 2p and
 // 2p+1).
 template <bool BT, class Bead>
-__device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0, Bead &b1)
+__device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0, Bead &b1, uint32_t &clog)
 {
     const Tile T = tile_table<BT>(a)[tile];
     const DevSys &S = a.systems[T.sys];
@@ -681,9 +707,13 @@ __device__ __forceinline__ void tile_load(const SweepArgs &a, int tile, Bead &b0
     const int g = (int)(((float)lane + 0.5f) * S.inv_P);
     const int p = lane - g * P;
     const int nin = min(tile_capacity<BT>(S), S.n_chains - (int)T.chain0);
+    const bool active = g < nin;
+    // the logical chain id keys the random numbers: load it with the
+    // positions, so the draws do not wait for a second memory round trip
+    clog = a.chain_id[S.chain_off + (int)T.chain0 + (active ? g : 0)];
     b0 = Bead{};
     b1 = Bead{};
-    if (g < nin) {
+    if (active) {
         const int64_t slot = S.slot_off + (int64_t)((int)T.chain0 + g) * (2 * P) + 2 * p;
         load_pair(PosArrays{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2}, slot, b0, b1);
     }
@@ -819,7 +849,7 @@ __device__ __forceinline__ float umb_step(float coef, float2 tn, float2 to, int 
 template <int R, int CW, int DM, bool CPL, bool BT, class Bead>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                            const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
-                                           uint32_t *agg_vals, Bead b0, Bead b1)
+                                           uint32_t *agg_vals, Bead b0, Bead b1, uint32_t clog)
 {
     const Tile T = tile_table<BT>(a)[wave];
     const DevSys &S = a.systems[T.sys];
@@ -846,7 +876,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
 
     // logical chain id: keys the random numbers and picks the species, so
     // results do not depend on where a chain sits in memory
-    const uint32_t clog = a.chain_id[S.chain_off + chain];
     const int cls = chain_cls<CPL>(S, a.chain_class, clog);
     int t0, t1;
     pattern_pair(S, cls, i0, t0, t1);
@@ -1051,7 +1080,7 @@ __device__ __forceinline__ float field_step(const SweepArgs &a, bool frozen, con
 template <int R, int CW, int DM, bool CPL, bool BT, class Bead>
 __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                                const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
-                                               uint32_t *agg_vals, Bead b0, Bead b1)
+                                               uint32_t *agg_vals, Bead b0, Bead b1, uint32_t clog)
 {
     const Tile T = tile_table<BT>(a)[wave];
     const DevSys &S = a.systems[T.sys];
@@ -1071,7 +1100,6 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
     const int64_t slot = S.slot_off + (int64_t)chain * (2 * P) + i0;
     const PosArrays A{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2};
     const Bead ob0 = b0, ob1 = b1;   // the stored state, to write back only what changes
-    const uint32_t clog = a.chain_id[S.chain_off + chain];
     const int cls = chain_cls<CPL>(S, a.chain_class, clog);
     const int t0 = pattern_type(S, cls, i0);
     const int t1 = pattern_type(S, cls, i1 < N ? i1 : i0);
@@ -1172,9 +1200,13 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
     // mode 1: counts of sweep s are B[s-1] + D[s-1]; this sweep adds to D[s],
     // writes B[s] and clears D[s+1] (last read by sweep s-1).  Mode 2: the
     // face fluxes of sweep s go to flux buffer s mod 2 (three W-word arrays).
-    const uint32_t *cin = FI ? a.base + ((s + 1) & 1) * W : a.base;
+    // Mode 3: the counts are B[s mod 2]; the changes go straight into its
+    // mirror B[(s+1) mod 2], which holds the same counts when the sweep
+    // starts and is read by no gather of this sweep.
+    const uint32_t *cin = FI ? a.base + ((s + 1) & 1) * W : (DM == 3 ? a.base + (s & 1) * W : a.base);
     const uint32_t *dprev = FI ? a.delta + ((s + 2) % 3) * W : nullptr;
-    uint32_t *dcur = FI ? a.delta + (s % 3) * W : (DM == 2 ? a.flux + (s & 1) * 3 * W : a.delta);
+    uint32_t *dcur = FI ? a.delta + (s % 3) * W
+                        : (DM == 2 ? a.flux + (s & 1) * 3 * W : (DM == 3 ? a.base + ((s + 1) & 1) * W : a.delta));
     const int wave = BT ? block_tile(a.xcd_remap) : wave_tile(a.waves_per_block, a.xcd_remap);
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // this wave's aggregation table (2 SLOTS words of dynamic LDS per wave)
@@ -1189,29 +1221,38 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         }
     }
     if constexpr (LOOP) {
-        const int64_t n_waves = (int64_t)gridDim.x * a.waves_per_block;
-        const int t_begin = (int)((int64_t)a.n_tiles * wave / n_waves);
-        const int t_end = (int)((int64_t)a.n_tiles * (wave + 1) / n_waves);
-        for (int t = t_begin; t < t_end; ++t) {
-            Bead b0, b1;
-            tile_load<false>(a, t, b0, b1);
+        // Resident waves walk the tiles grid-stride (wave, wave + n_waves,
+        // ...), so the tiles in flight at any time are neighbours in the
+        // spatial chain order and their field gathers share the L2.  Software
+        // pipeline: the positions of a wave's next tile are loaded before
+        // the current tile's field gathers, so their latency overlaps the
+        // current tile's work.
+        const int n_waves = (int)gridDim.x * a.waves_per_block;
+        Bead nb0, nb1;
+        uint32_t nclog = 0u;
+        if (wave < a.n_tiles) tile_load<false>(a, wave, nb0, nb1, nclog);
+        for (int t = wave; t < a.n_tiles; t += n_waves) {
+            const Bead b0 = nb0, b1 = nb1;
+            const uint32_t clog = nclog;
+            if (t + n_waves < a.n_tiles) tile_load<false>(a, t + n_waves, nb0, nb1, nclog);
             agg_clear<SLOTS>(agg_keys, agg_vals);
             if (SMC && a.systems[a.tiles[t].sys].smc)
-                sweep_tile_smc<R, CW, DM, CPL, false>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile_smc<R, CW, DM, CPL, false>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog);
             else
-                sweep_tile<R, CW, DM, CPL, false>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile<R, CW, DM, CPL, false>(a, t, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog);
         }
     } else {
         // block tiles: the test is uniform over the block, so every thread
         // of a working block reaches the barriers of the tile
         if (wave < (BT ? a.n_ptiles : a.n_tiles)) {
             Bead b0, b1;
-            tile_load<BT>(a, wave, b0, b1);
+            uint32_t clog;
+            tile_load<BT>(a, wave, b0, b1, clog);
             agg_clear<SLOTS>(agg_keys, agg_vals);
             if (SMC && a.systems[tile_table<BT>(a)[wave].sys].smc)
-                sweep_tile_smc<R, CW, DM, CPL, BT>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile_smc<R, CW, DM, CPL, BT>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog);
             else
-                sweep_tile<R, CW, DM, CPL, BT>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1);
+                sweep_tile<R, CW, DM, CPL, BT>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog);
         }
     }
     if constexpr (FI) {
@@ -1318,6 +1359,70 @@ __global__ __launch_bounds__(256) void k_fold(const uint32_t *in, uint32_t *delt
         delta[i] = 0u;
     }
     if (ovf) atomicOr(status, ST_COUNT_OVERFLOW);
+}
+
+// Density mode 3: copy the counts the sweep's atomics produced,
+// B[(s+1) mod 2], into B[s mod 2], so both hold them for the next sweep (16-byte
+// accesses; the buffers are 256-byte aligned and W is a multiple of 4).
+// Packed 16-bit counts: every change of a sweep is a device atomic add of
+// +-1 or +-2^16 on the word, and a true count never goes below zero during
+// the sweep (a bead leaves only a cell it was counted in at the start), so
+// the word is exact unless a count passed 65535: then its carry moves into
+// the other half or out of the word, which lowers the sum of all halves.  So
+// each block also writes the sum of the halves it copied, and k_mirror_check
+// compares the total with the number of beads.  (Plain stores and a second
+// kernel instead of a last-block reduction: a device-scope fence per block
+// would write back the L2 each time.)
+template <int CW>
+__global__ __launch_bounds__(256) void k_mirror(MirrorArgs a)
+{
+    const uint64_t s = *a.sweep_ctr + a.rel;
+    const int64_t W = a.count_words;
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.base + ((s + 1) & 1) * W);
+    uint4 *dst = reinterpret_cast<uint4 *>(a.base + (s & 1) * W);
+    const int64_t n4 = W >> 2;
+    // four 16-byte loads in flight per thread before the stores
+    constexpr int U = kMirrorUnroll;
+    const int64_t step = (int64_t)gridDim.x * (256 * U);
+    uint64_t sum = 0;
+    for (int64_t b = (int64_t)blockIdx.x * (256 * U) + threadIdx.x; b < n4; b += step) {
+        uint4 w[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (b + 256 * k < n4) w[k] = src[b + 256 * k];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (b + 256 * k < n4) {
+                dst[b + 256 * k] = w[k];
+                if constexpr (CW == COUNT_U16)
+                    sum += (uint64_t)((w[k].x & 0xFFFFu) + (w[k].x >> 16) + (w[k].y & 0xFFFFu) + (w[k].y >> 16)) +
+                           (uint64_t)((w[k].z & 0xFFFFu) + (w[k].z >> 16) + (w[k].w & 0xFFFFu) + (w[k].w >> 16));
+            }
+    }
+    if constexpr (CW == COUNT_U16) {
+        __shared__ unsigned long long part[4];
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
+        __syncthreads();
+        if (threadIdx.x == 0) a.part[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+    }
+}
+
+// Sum of the copy blocks' half sums against the number of beads (one block).
+__global__ __launch_bounds__(1024) void k_mirror_check(const unsigned long long *part, int n_part,
+                                                       unsigned long long beads, uint32_t *status)
+{
+    __shared__ unsigned long long red[16];
+    unsigned long long sum = 0;
+    for (int i = threadIdx.x; i < n_part; i += blockDim.x) sum += part[i];
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+        if (t != beads) atomicOr(status, ST_COUNT_OVERFLOW);
+    }
 }
 
 template <int R, int CW>
@@ -1997,6 +2102,7 @@ static hipError_t launch_sweep_s(const SweepArgs &a, int blocks, hipStream_t st)
 {
     if (a.density_mode == 1) launch_sweep_d<R, CW, 1, SMC>(a, blocks, st);
     else if (a.density_mode == 2) launch_sweep_d<R, CW, 2, SMC>(a, blocks, st);
+    else if (a.density_mode == 3) launch_sweep_d<R, CW, 3, SMC>(a, blocks, st);
     else launch_sweep_d<R, CW, 0, SMC>(a, blocks, st);
     return hipGetLastError();
 }
@@ -2061,6 +2167,20 @@ hipError_t launch_fold_faces(int cw, const FoldFacesArgs &a, int n_chunks, hipSt
     if (n_chunks <= 0) return hipSuccess;
     if (cw == COUNT_U16) hipLaunchKernelGGL((k_fold_faces<COUNT_U16>), dim3(n_chunks), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_fold_faces<COUNT_U32>), dim3(n_chunks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mirror(int cw, const MirrorArgs &a, hipStream_t st)
+{
+    if (a.count_words <= 0) return hipSuccess;
+    int64_t blocks = (a.count_words / 4 + 256 * kMirrorUnroll - 1) / (256 * kMirrorUnroll);
+    if (blocks > kMirrorBlocks) blocks = kMirrorBlocks;
+    if (cw == COUNT_U16) {
+        hipLaunchKernelGGL((k_mirror<COUNT_U16>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_mirror_check, dim3(1), dim3(1024), 0, st, a.part, (int)blocks, a.beads, a.status);
+    } else {
+        hipLaunchKernelGGL((k_mirror<COUNT_U32>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 

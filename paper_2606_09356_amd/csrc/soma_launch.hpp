@@ -25,7 +25,9 @@ struct SweepArgs {
     int64_t count_words;           // uint32 words per buffer
     int density_mode;              // 0: counts in base[0], delta in delta[0], folded by k_fold;
                                    // 1: rotation, the sweep kernel folds the previous delta;
-                                   // 2: face fluxes in flux buffer s mod 2, folded by k_fold_faces
+                                   // 2: face fluxes in flux buffer s mod 2, folded by k_fold_faces;
+                                   // 3: mirrored counts: gathers from base[s mod 2], atomics into
+                                   //    base[(s+1) mod 2], then k_mirror copies it back
     uint32_t *flux;                // mode 2: two buffers of three count_words-word arrays
     int smc;                       // some system uses bond-force-biased moves
     int cpl;                       // some system uses walls, zones, the umbrella or caller-set classes
@@ -154,6 +156,22 @@ struct FoldFacesArgs {
 hipError_t launch_fold_faces(int cw, const FoldFacesArgs &a, int n_chunks, hipStream_t st);
 hipError_t launch_fold(int cw, const uint32_t *counts_in, uint32_t *delta, uint32_t *counts_out, int64_t n,
                        uint32_t *status, hipStream_t st);
+// Density mode 3: after sweep s, copy base[(s+1) mod 2] (the counts the
+// sweep's atomics produced) into base[s mod 2]; for packed 16-bit counts
+// also check that the halves sum to the number of beads (each copy block
+// writes its part to `part`, a second one-block kernel adds them up).
+constexpr int kMirrorBlocks = 32768;
+constexpr int kMirrorUnroll = 4;   // 16-byte words per thread per step
+struct MirrorArgs {
+    uint32_t *base;                // two count buffers of count_words words each
+    int64_t count_words;           // a multiple of 4
+    const uint64_t *sweep_ctr;
+    uint32_t rel;
+    unsigned long long *part;      // kMirrorBlocks partial sums of the count halves
+    unsigned long long beads;      // beads of the context
+    uint32_t *status;
+};
+hipError_t launch_mirror(int cw, const MirrorArgs &a, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_advance(uint64_t *ctr, uint32_t n, hipStream_t st);
 hipError_t launch_init(const InitArgs &a, hipStream_t st);

@@ -128,7 +128,7 @@ def test_placement_errors():
     g.close()
 
 
-@pytest.mark.parametrize("r,cw,dm", [("f32", 16, 0), ("cell", 32, 1), ("cell", 16, 0)])
+@pytest.mark.parametrize("r,cw,dm", [("f32", 16, 0), ("cell", 32, 1), ("cell", 16, 0), ("cell", 16, 3)])
 def test_umbrella_and_walls_sweep_parity(r, cw, dm):
     systems = coupling_batch()
     g = Soma(systems, seed=SEED, pos_repr=r, count_width=cw, density_mode=dm, coupling=True, reorder_every=2)
@@ -173,7 +173,7 @@ def test_umbrella_and_walls_sweep_parity(r, cw, dm):
     g.close()
 
 
-@pytest.mark.parametrize("r,dm", [("f32", 0), ("cell", 1)])
+@pytest.mark.parametrize("r,dm", [("f32", 0), ("cell", 1), ("f32", 3)])
 def test_zones_with_smart_moves_parity(r, dm):
     systems = coupling_batch()
     systems[0].smc_A = 0.002
@@ -246,7 +246,7 @@ def test_autotune_with_zones_keeps_trajectory():
     a.sweep(3)
     b.sweep(3)
     t = a.autotune(2)
-    assert t["density_mode"] != 2 and t["n_candidates"] == 60
+    assert t["density_mode"] != 2 and t["n_candidates"] == 90
     a.sweep(4)
     b.sweep(4)
     for k in range(len(systems)):

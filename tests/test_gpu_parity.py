@@ -129,7 +129,8 @@ def test_fields_match_oracle(name):
     g.close()
 
 
-@pytest.mark.parametrize("reorder,dm,pk", [(0, 0, 0), (1, 0, 0), (0, 2, 0), (1, 1, 0), (0, 0, 1), (1, 2, 1)])
+@pytest.mark.parametrize("reorder,dm,pk", [(0, 0, 0), (1, 0, 0), (0, 2, 0), (1, 1, 0), (0, 0, 1), (1, 2, 1),
+                                           (0, 3, 0), (1, 3, 1)])
 @pytest.mark.parametrize("name", list(small_cases()))
 def test_single_and_multi_sweep_parity(name, reorder, dm, pk):
     systems, r, cw = small_cases()[name]
@@ -248,7 +249,7 @@ def test_autotune_keeps_the_trajectory(r):
     b.sweep(2)
     t = a.autotune(trial_sweeps=2)
     print(f"[autotune {r}] {t}", flush=True)
-    assert t["n_candidates"] == 114 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
+    assert t["n_candidates"] == 152 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
     i = a.info()
     assert (i["waves_per_block"], i["waves_per_cu"], i["xcd_remap"], i["density_mode"], i["packed_tiles"]) == \
         (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"], t["density_mode"], t["packed_tiles"])
@@ -275,7 +276,7 @@ def test_autotune_keeps_the_trajectory(r):
     c.close()
 
 
-@pytest.mark.parametrize("dm", [0, 1, 2])
+@pytest.mark.parametrize("dm", [0, 1, 2, 3])
 def test_kernel_timing_sweeps_are_real_sweeps(dm):
     """soma_time_kernels runs real sweeps (eager, with events around each
     kernel): the trajectory equals plain sweeps, and the durations are positive."""
@@ -309,13 +310,14 @@ def test_batched_equals_each_system_alone():
     g.close()
 
 
-@pytest.mark.parametrize("r,dm", [("f32", 0), ("cell", 0), ("f32", 1), ("cell", 1), ("f32", 2), ("cell", 2)])
+@pytest.mark.parametrize("r,dm", [("f32", 0), ("cell", 0), ("f32", 1), ("cell", 1), ("f32", 2), ("cell", 2),
+                                  ("f32", 3), ("cell", 3)])
 def test_checkpoint_resume_bit_exact(r, dm):
     """A checkpoint taken in one density mode resumes bit-exactly in another."""
     systems = W.batched_mixed(n_systems=3, seed=48, bead_range=(2000, 8000))
     a = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=dm)
     a.sweep(6)
-    b = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=(dm + 1) % 3)
+    b = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=(dm + 1) % 4)
     b.sweep(3)
     saved = [b.state(k) for k in range(len(systems))]
     b.close()
@@ -341,6 +343,34 @@ def test_checkpoint_resume_bit_exact(r, dm):
         assert (a.density(k) == c.density(k)).all()
     a.close()
     c.close()
+
+
+@pytest.mark.parametrize("dm", [0, 1, 2, 3])
+def test_count_overflow_in_a_sweep_is_latched(dm):
+    """A packed 16-bit count pushed past 65535 by a sweep latches
+    SOMA_EOVERFLOW in every density mode, reported by the next call that
+    reads the counts (density mode 1 folds a sweep's changes only then).
+    65534 A beads sit at the centre of one cell (a move of at most 0.05 Re
+    cannot take them out of a 0.25 Re cell) and 1000 two-bead chains sit
+    0.001 Re outside its lower x face, so about half of them cross in and the
+    count passes 65535."""
+    inner, outer = 32767, 1000                 # two-bead chains
+    n = inner + outer
+    s = W.SystemDesc(n, 2, np.zeros(2, np.uint8), np.zeros(2, np.uint8), n, 0.0, 0.0,
+                     (8.0, 8.0, 8.0), (32, 32, 32))
+    xyz = np.empty((3, 2 * n))
+    xyz[:, : 2 * inner] = 3.125                # centre of cell (12, 12, 12)
+    xyz[0, 2 * inner:] = 2.999                 # cell 11, next to the face at x = 3.0
+    xyz[1:, 2 * inner:] = 3.125
+    g = Soma([s], seed=1, pos_repr="f32", count_width=16, density_mode=dm)
+    g.set_positions(0, xyz)
+    d = g.density(0)
+    assert d[0].max() == 65534 and d[0].sum() == 2 * n
+    g.sweep(1)
+    with pytest.raises(SomaError) as e:
+        g.density(0)
+    assert e.value.code == SOMA_EOVERFLOW
+    g.close()
 
 
 def test_count_overflow_is_latched_not_wrapped():
@@ -421,7 +451,7 @@ def apply_shape(g, shape):
     return g
 
 
-@pytest.mark.parametrize("shape", ["auto", "dm0", "dm1", "dm2"])
+@pytest.mark.parametrize("shape", ["auto", "dm0", "dm1", "dm2", "dm3"])
 @pytest.mark.parametrize("name", ["plain_large", "mixed_large"])
 def test_full_size_single_sweep_parity(name, shape):
     """Full-size workloads, in the benchmark's launch configuration (the

@@ -9,8 +9,8 @@ the FP64 oracle, and sampled full-size parity of the batched workloads.
   about 4e-6 Re, while the cell form keeps 1.5e-8 Re.
 * Equilibrium: in a disordered melt, after equilibration, time averages of
   Re^2, Rg^2, bond and non-bonded energy per chain agree with the FP64
-  oracle within 0.5 %, and Re^2, Rg^2 within two combined chain-level
-  standard errors.
+  oracle within two combined standard errors (block averages over blocks
+  of at least twice the correlation time) and within 0.5 %.
 * Full size, batched: one sweep of the 64- and 256-system workloads in the
   benchmark's launch configuration (autotuned) and in density modes 1 and 2;
   for sampled systems the oracle starts
@@ -32,6 +32,14 @@ SEED = 20260609
 
 def rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
+
+
+# Measured errors of the two representations on this case (10 sweeps): FP32
+# Re^2 1.5e-5, Rg^2 2.0e-6, E_b 9.4e-6; cell + offset 1.1e-10, 1.7e-10,
+# 1.9e-9.  Each bound sits about 10x above its measurement, so a regression
+# of one representation toward the other's precision fails.
+PRECISION_BOUND = {"f32": {"Re2": 1.5e-4, "Rg2": 2e-5, "Ebond_per_chain": 1e-4},
+                   "cell": {"Re2": 1e-9, "Rg2": 2e-9, "Ebond_per_chain": 2e-8}}
 
 
 def test_precision_error_against_fp64_positions():
@@ -57,51 +65,95 @@ def test_precision_error_against_fp64_positions():
     print(f"[precision] max relative error over 10 sweeps vs FP64 positions: {worst}")
     for name in worst:
         for k, v in worst[name].items():
-            assert v < 2e-3, (name, k, v)
+            assert v < PRECISION_BOUND[name][k], (name, k, v)
     g32.close()
     gc.close()
 
 
-@pytest.mark.parametrize("r", ["f32", "cell"])
-def test_equilibrium_observables_agree_with_oracle(r):
-    """Disordered melt (chiN = 10 < 10.5), N = 16, 32768 chains: after 200
-    sweeps of equilibration, time averages over 400 sweeps agree within two
-    combined chain-level standard errors and within 0.5 %."""
-    s = W.diblock_system(32768, 16, 0.5, 10.0, 50.0, (16.0, 16.0, 16.0), (64, 64, 64))
+def tau_int(x):
+    """Integrated autocorrelation time of a series, in samples, with Sokal's
+    automatic window (the smallest W with W >= 5 tau(W))."""
+    x = np.asarray(x, float) - np.mean(x)
+    n = len(x)
+    f = np.fft.rfft(x, 2 * n)
+    ac = np.fft.irfft(f * np.conj(f))[:n]
+    ac = ac / ac[0]
+    t = 0.5
+    for w in range(1, n):
+        t += ac[w]
+        if w >= 5 * t:
+            break
+    return t
+
+
+def block_mean_sigma(x, block):
+    """Mean of the series and the standard error of the mean from the
+    variance of its block means."""
+    nb = len(x) // block
+    b = np.asarray(x[: nb * block], float).reshape(nb, block).mean(axis=1)
+    return float(b.mean()), float(b.std(ddof=1) / math.sqrt(nb)), nb
+
+
+def test_equilibrium_observables_agree_with_oracle():
+    """Equilibrium agreement with the FP64-position oracle (time averages of
+    Re^2, Rg^2, bond and non-bonded energy per chain), for both position
+    representations, in a disordered melt (chiN = 10, N = 8, 32768 chains,
+    trial cube half-width 0.2 Re so the chains relax in about a hundred
+    sweeps).  After 1500 sweeps of equilibration, observables are sampled
+    every 5 sweeps for 6000 sweeps; the integrated autocorrelation time tau of
+    the chain size (the slowest of the Re^2 and Rg^2 series, at least 200
+    sweeps) sets the block length for every observable (3 tau, above the 2 tau
+    the reading of the tolerance asks for, and at least 8 blocks); the standard
+    error of each time average is the spread of its block means.  Pass:
+    |GPU - oracle| <= 2 sqrt(s_GPU^2 + s_oracle^2) and within 0.5 %.  (The
+    system is sized so that the Re^2 difference has a standard error near
+    0.15 %, well inside the 0.5 % cap.)"""
+    s = W.diblock_system(32768, 8, 0.5, 10.0, 50.0, (16.0, 16.0, 8.0), (64, 64, 32), move_halfwidth=0.2)
     xyz = W.gaussian_walks(s, seed=22)
+    burn, total, every = 1500, 6000, 5
+    keys = ("Re2", "Rg2", "Ebond_per_chain", "Enb_per_chain")
     o = oracle.OracleSystem(s, sys_id=0, mode=oracle.MODE_F64)
     o.set_positions(xyz)
-    g = Soma([s], seed=SEED, pos_repr=r, count_width=16, reorder_every=50)
-    g.set_positions(0, xyz)
-    burn, snaps, every = 200, 20, 20
+    gs = {r: Soma([s], seed=SEED, pos_repr=r, count_width=16, reorder_every=50) for r in ("f32", "cell")}
+    for g in gs.values():
+        g.set_positions(0, xyz)
+        g.sweep(burn)
     o.run(SEED, 0, burn)
-    g.sweep(burn)
-    keys = ("Re2", "Rg2", "Ebond_per_chain", "Enb_per_chain")
-    gs = {k: [] for k in keys + ("Re2_err", "Rg2_err")}
-    os_ = {k: [] for k in keys + ("Re2_err", "Rg2_err")}
+    series = {"oracle": {k: [] for k in keys}, "f32": {k: [] for k in keys}, "cell": {k: [] for k in keys}}
     sweep = burn
-    for _ in range(snaps):
+    for _ in range(total // every):
         o.run(SEED, sweep, every)
-        g.sweep(every)
         sweep += every
-        go, oo = g.observables(0), o.observables()
-        for k in gs:
-            gs[k].append(go[k])
-            os_[k].append(oo[k])
+        oo = o.observables()
+        for k in keys:
+            series["oracle"][k].append(oo[k])
+        for r, g in gs.items():
+            g.sweep(every)
+            go = g.observables(0)
+            for k in keys:
+                series[r][k].append(go[k])
+    for g in gs.values():
+        g.close()
+    # one correlation time for every observable: the slowest of the chain-size
+    # series (Re^2, Rg^2) of the three trajectories, at least 200 sweeps (the
+    # energies carry the same slow chain-size modes under faster noise)
+    tau = max([tau_int(series[src][k]) for src in series for k in ("Re2", "Rg2")] + [200 / every])
+    block = max(int(math.ceil(3 * tau)), 1)
     for k in keys:
-        a, b = float(np.mean(gs[k])), float(np.mean(os_[k]))
-        diff = abs(a - b)
-        if k in ("Re2", "Rg2"):
-            se = math.sqrt(np.mean(gs[k + "_err"]) ** 2 + np.mean(os_[k + "_err"]) ** 2)
-            print(f"[equilibrium {r}] {k}: gpu {a:.6f} oracle {b:.6f} diff {diff:.2e} 2se {2 * se:.2e}")
-            assert diff <= 2 * se, (k, diff, se)
-        else:
-            print(f"[equilibrium {r}] {k}: gpu {a:.6f} oracle {b:.6f} rel diff {diff / abs(b):.2e}")
-        assert diff <= 5e-3 * abs(b), (k, diff)
-    g.close()
+        assert len(series["oracle"][k]) // block >= 8, (k, tau, block)
+        mo, so, nb = block_mean_sigma(series["oracle"][k], block)
+        for r in ("f32", "cell"):
+            mg, sg, _ = block_mean_sigma(series[r][k], block)
+            diff = abs(mg - mo)
+            bound = 2 * math.sqrt(sg ** 2 + so ** 2)
+            print(f"[equilibrium {r}] {k}: gpu {mg:.6f} +- {sg:.1e}, oracle {mo:.6f} +- {so:.1e}, "
+                  f"tau {tau * every:.0f} sweeps, {nb} blocks of {block * every} sweeps: diff {diff:.2e} "
+                  f"(2 sigma {bound:.2e}, rel {diff / abs(mo):.2e})")
+            assert diff <= bound, (r, k, diff, bound)
+            assert diff <= 5e-3 * abs(mo), (r, k, diff)
 
 
-@pytest.mark.parametrize("shape", ["auto", "dm1", "dm2", "packed"])
+@pytest.mark.parametrize("shape", ["auto", "dm1", "dm2", "dm3", "packed"])
 @pytest.mark.parametrize("name,sample", [("batched_uneven", [0, 17, 63]), ("batched_mixed", [0, 101, 255])])
 def test_full_size_batched_sampled_parity(name, sample, shape):
     """One sweep of the full batched workloads in the benchmark's launch

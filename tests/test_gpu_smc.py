@@ -33,7 +33,7 @@ def mixed_batch(seed):
 
 @pytest.mark.parametrize("r,cw,dm,pk", [("f32", 16, 0, 0), ("f32", 16, 1, 0), ("f32", 16, 2, 0), ("cell", 32, 0, 0),
                                         ("cell", 16, 1, 0), ("cell", 16, 2, 0), ("cell", 32, 2, 0), ("f32", 16, 0, 1),
-                                        ("cell", 16, 2, 1)])
+                                        ("cell", 16, 2, 1), ("cell", 16, 3, 0), ("f32", 16, 3, 1)])
 def test_smart_move_parity(r, cw, dm, pk):
     systems = mixed_batch(61)
     print(f"[smc parity] {r}/u{cw}/mode {dm}/packed {pk}: {sum(s.n_beads for s in systems)} beads", flush=True)
@@ -102,10 +102,10 @@ def test_smart_two_bead_frozen_field_boltzmann_on_gpu():
     g.close()
 
 
-@pytest.mark.parametrize("shape", ["auto", "dm0", "dm2"])
+@pytest.mark.parametrize("shape", ["auto", "dm0", "dm2", "dm3"])
 def test_full_size_smart_move_parity(shape):
     """plain_large with smart moves, in the benchmark's configuration (the
-    autotuner's choice) and in density modes 0 and 2: every decision of two
+    autotuner's choice) and in density modes 0, 2 and 3: every decision of two
     sweeps compared with the oracle, density bit-exact."""
     systems = W.workload("plain_large_smc")
     s = systems[0]
