@@ -64,7 +64,7 @@ typedef enum {
 /* Position representations. */
 enum {
     SOMA_POS_F32 = 0,      /* unwrapped FP32 coordinates, 12 B per bead */
-    SOMA_POS_CELL_F32 = 1  /* int32 unwrapped cell + FP32 offset in [0, edge), 24 B per bead */
+    SOMA_POS_CELL_F32 = 1  /* int32 unwrapped cell + FP32 offset (in [-edge, 2 edge)), 24 B per bead */
 };
 /* Density count widths. */
 enum {
@@ -279,7 +279,12 @@ int soma_set_positions(soma_ctx *ctx, int32_t sys, const double *xyz);
 /* Raw stored state of system `sys`, for exact checkpoints.
  * SOMA_POS_F32: f32 = float [3][n_chains*N], cell = NULL.
  * SOMA_POS_CELL_F32: cell = int32 [3][n_chains*N], f32 = float offsets
- * [3][n_chains*N].  Host memory.  soma_set_state rebuilds the density. */
+ * [3][n_chains*N]; a bead sits at cell * edge + offset.  A new position
+ * has its offset in [0, edge); a trial move keeps the offset anywhere in
+ * [-edge, 2 edge) and steps the cell only when it leaves that window (so a
+ * sweep rewrites few cell words); the NGP cell is floor(offset / edge) +
+ * cell.  soma_set_state takes offsets in [-edge, 2 edge) (SOMA_EINVAL
+ * otherwise).  Host memory.  soma_set_state rebuilds the density. */
 int soma_get_state(soma_ctx *ctx, int32_t sys, float *f32, int32_t *cell);
 int soma_set_state(soma_ctx *ctx, int32_t sys, const float *f32, const int32_t *cell);
 

@@ -40,8 +40,9 @@
  * Position modes
  *   0  FP64 positions (reference for observables and precision errors)
  *   1  positions stored as FP32; all energies in FP64
- *   2  positions stored as int32 cell + FP32 offset in [0, cell edge);
- *      all energies in FP64
+ *   2  positions stored as int32 cell + FP32 offset: a new position in
+ *      [0, cell edge), after trial moves anywhere in [-edge, 2 edge) (a cell
+ *      step only when the offset leaves that window); all energies in FP64
  * Modes 1 and 2 reproduce the storage rounding of the GPU representation so
  * that single-sweep decisions and density histograms can be compared one by
  * one; they take every rounding step explicitly with C float arithmetic.
@@ -157,13 +158,32 @@ static double get_pos(const orc_system *s, const orc_state *st, int d, int64_t b
     }
 }
 
-/* Mode 2 renormalisation: keep the offset in [0, edge) by moving whole
- * cells.  Every step is one FP32 rounding, and an offset that rounds up to
- * exactly one edge goes to offset 0 of the next cell. */
+/* Mode 2, canonical form of a new position: the offset in [0, edge), by
+ * moving whole cells.  Every step is one FP32 rounding, and an offset that
+ * rounds up to exactly one edge goes to offset 0 of the next cell. */
 static void renorm_cell(int32_t *c, float *o, float edge)
 {
     while (*o < 0.0f) { *o = *o + edge; *c -= 1; }
     while (*o >= edge) { *o = *o - edge; *c += 1; }
+}
+
+/* Mode 2, after a trial move (the paper does not describe the storage; this
+ * is the representation's own rule): the offset may lie anywhere in the
+ * window [-edge, 2 edge); an offset that
+ * leaves it moves one whole cell, one FP32 rounding (a trial move is below
+ * one edge, so one step brings it back).  The stored (cell, offset) pair
+ * still names the same point c e + o. */
+static void renorm_window(int32_t *c, float *o, float edge)
+{
+    if (*o < -edge) { *o = *o + edge; *c -= 1; }
+    else if (*o >= 2.0f * edge) { *o = *o - edge; *c += 1; }
+}
+
+/* Mode 2: unwrapped NGP index along axis d of the stored pair: floor((c e + o) / e)
+ * = c + floor(o / e) exactly, which for o in [-e, 2e) is c - 1, c or c + 1. */
+static int64_t cell_index(int32_t c, float o, float edge)
+{
+    return (int64_t)c + (o >= edge ? 1 : 0) - (o < 0.0f ? 1 : 0);
 }
 
 /* Quantise FP64 positions into the state's representation. */
@@ -228,7 +248,7 @@ static int64_t cell_of(const orc_system *s, const orc_state *st, int64_t b)
     for (int d = 0; d < 3; ++d) {
         int64_t i;
         if (st->mode == 2)
-            i = st->cell[d * B + b];
+            i = cell_index(st->cell[d * B + b], st->off[d * B + b], (float)cell_edge(s, d));
         else
             i = ngp_index(s, d, get_pos(s, st, d, b));
         idx[d] = wrap_index(i, s->grid[d]);
@@ -372,7 +392,8 @@ static int has_zones(const orc_system *s) { return has_walls(s) && (s->zone[0] >
 /* Unwrapped z cell of bead b in the stored representation. */
 static int64_t z_cell(const orc_system *s, const orc_state *st, int64_t b)
 {
-    if (st->mode == 2) return st->cell[2 * n_beads(s) + b];
+    if (st->mode == 2)
+        return cell_index(st->cell[2 * n_beads(s) + b], st->off[2 * n_beads(s) + b], (float)cell_edge(s, 2));
     return ngp_index(s, 2, get_pos(s, st, 2, b));
 }
 
@@ -472,7 +493,7 @@ uint64_t orc_sweep(const orc_system *s, orc_state *st, uint64_t seed, uint32_t s
                         float edge = (float)cell_edge(s, a);
                         c_new[a] = st->cell[a * B + b];
                         o_new[a] = st->off[a * B + b] + d[a];
-                        renorm_cell(&c_new[a], &o_new[a], edge);
+                        renorm_window(&c_new[a], &o_new[a], edge);
                         r_new[a] = (double)c_new[a] * (double)edge + (double)o_new[a];
                     }
                 }
@@ -502,7 +523,7 @@ uint64_t orc_sweep(const orc_system *s, orc_state *st, uint64_t seed, uint32_t s
                 for (int a = 0; a < 3; ++a) {
                     int64_t ia;
                     if (st->mode == 2)
-                        ia = c_new[a];
+                        ia = cell_index(c_new[a], o_new[a], (float)cell_edge(s, a));
                     else
                         ia = ngp_index(s, a, r_new[a]);
                     /* walls (Sec. 3.2, wall confinement): a trial position whose

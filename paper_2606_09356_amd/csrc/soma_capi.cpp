@@ -1322,7 +1322,8 @@ int soma_set_state(soma_ctx *c, int32_t sys, const float *f32, const int32_t *ce
                 if (!std::isfinite(v)) return fail(c, SOMA_EINVAL, "state values must be finite");
                 if (c->repr == soma::REPR_CELL) {
                     const int cv = cell[a * B + ch * N + i];
-                    if (!(v >= 0.0f && v < h.dev.edge[a])) return fail(c, SOMA_EINVAL, "offsets must lie in [0, edge)");
+                    if (!(v >= -h.dev.edge[a] && v < 2.0f * h.dev.edge[a]))
+                        return fail(c, SOMA_EINVAL, "offsets must lie in [-edge, 2 edge)");
                     if (cv <= -(1 << 22) || cv >= (1 << 22)) return fail(c, SOMA_EINVAL, "cell index out of range (|cell| < 2^22)");
                     Cv[a][s] = cv;
                 }

@@ -169,30 +169,36 @@ __device__ __forceinline__ void renorm(int &c, float &o, float e)
     while (o >= e) { o = o - e; c += 1; }
 }
 
-// renorm for a trial offset o + d with |d| < 0.99 edge: at most one step
-// down and one step up, each the same FP32 operation as in renorm, so the
-// result is identical (branch-free)
-__device__ __forceinline__ void renorm1(int &c, float &o, float e)
+// Lazy renormalisation of a trial offset o + d (|d| < 0.99 edge): the
+// offset may lie anywhere in the window [-e, 2e); only an offset that leaves
+// it moves one whole cell (one FP32 rounding), which brings it back inside.
+// A bead's cell index therefore changes only after a net displacement of
+// about one edge, so a sweep rewrites few cell words (renorm, which keeps
+// offsets in [0, e), gives the canonical form of a new position).
+__device__ __forceinline__ void renorm_window(int &c, float &o, float e)
 {
-    const bool lo = o < 0.0f;
-    o = lo ? o + e : o;
-    c = lo ? c - 1 : c;
-    const bool hi = o >= e;
-    o = hi ? o - e : o;
-    c = hi ? c + 1 : c;
+    const bool lo = o < -e;
+    const bool hi = o >= 2.0f * e;
+    o = lo ? o + e : (hi ? o - e : o);
+    c += (int)hi - (int)lo;
 }
+
+// NGP index of a bead along one axis: floor((c e + o) / e) = c + floor(o / e)
+// exactly, with o in [-e, 2e).
+__device__ __forceinline__ int ngp(int c, float o, float e) { return c + (int)(o >= e) - (int)(o < 0.0f); }
 
 __device__ __forceinline__ BeadCell propose(const BeadCell &a, const Draw &d, const SysView &v)
 {
     BeadCell n{a.cx, a.cy, a.cz, a.ox + d.dx, a.oy + d.dy, a.oz + d.dz};
-    renorm1(n.cx, n.ox, v.e0);
-    renorm1(n.cy, n.oy, v.e1);
-    renorm1(n.cz, n.oz, v.e2);
+    renorm_window(n.cx, n.ox, v.e0);
+    renorm_window(n.cy, n.oy, v.e1);
+    renorm_window(n.cz, n.oz, v.e2);
     return n;
 }
 
 // NGP cell of a bead: wrapped cell coordinates and, for FP32 positions, the
-// unwrapped floors (to step to the cell of a trial position).  `bad` is set
+// unwrapped floors (to step to the cell of a trial position; for cell +
+// offset positions fz alone, the unwrapped z index).  `bad` is set
 // when the unwrapped index leaves the range the wrap handles (or the
 // coordinate is not finite); the bead is then counted in cell 0.
 struct CellPos {
@@ -228,19 +234,22 @@ __device__ __forceinline__ CellPos locate(const BeadF32 &a, const SysView &v, bo
     }
     return c;
 }
+// (cell mode: fz carries the unwrapped z index, for walls and zones)
 __device__ __forceinline__ CellPos locate(const BeadCell &a, const SysView &v, bool &bad)
 {
-    CellPos c{wrap_step(a.cx, v.n0), wrap_step(a.cy, v.n1), wrap_step(a.cz, v.n2), 0.0f, 0.0f, 0.0f};
+    const int kx = ngp(a.cx, a.ox, v.e0), ky = ngp(a.cy, a.oy, v.e1), kz = ngp(a.cz, a.oz, v.e2);
+    CellPos c{wrap_step(kx, v.n0), wrap_step(ky, v.n1), wrap_step(kz, v.n2), 0.0f, 0.0f, (float)kz};
     if (!(wrapped(c.x, v.n0) && wrapped(c.y, v.n1) && wrapped(c.z, v.n2))) {
-        if (a.cx <= -kCellLimit || a.cx >= kCellLimit || a.cy <= -kCellLimit || a.cy >= kCellLimit ||
-            a.cz <= -kCellLimit || a.cz >= kCellLimit) {
+        if (kx <= -kCellLimit || kx >= kCellLimit || ky <= -kCellLimit || ky >= kCellLimit ||
+            kz <= -kCellLimit || kz >= kCellLimit) {
             bad = true;
             c.x = c.y = c.z = 0;
+            c.fz = 0.0f;
             return c;
         }
-        c.x = wrap_cell(a.cx, v.n0, v.inv_n0);
-        c.y = wrap_cell(a.cy, v.n1, v.inv_n1);
-        c.z = wrap_cell(a.cz, v.n2, v.inv_n2);
+        c.x = wrap_cell(kx, v.n0, v.inv_n0);
+        c.y = wrap_cell(ky, v.n1, v.inv_n1);
+        c.z = wrap_cell(kz, v.n2, v.inv_n2);
     }
     return c;
 }
@@ -263,12 +272,13 @@ __device__ __forceinline__ CellPos step(const CellPos &o, const BeadF32 &, const
 }
 __device__ __forceinline__ CellPos step(const CellPos &o, const BeadCell &ob, const BeadCell &n, const SysView &v)
 {
-    // (a trial offset renormalises by at most one cell per axis, so the
-    // stored cells differ by -1, 0 or 1)
-    CellPos c{0, 0, 0, 0.0f, 0.0f, 0.0f};
-    c.x = wrap_step(o.x + (n.cx - ob.cx), v.n0);
-    c.y = wrap_step(o.y + (n.cy - ob.cy), v.n1);
-    c.z = wrap_step(o.z + (n.cz - ob.cz), v.n2);
+    // (a trial move is shorter than one cell edge, so the NGP index changes
+    // by -1, 0 or 1 per axis)
+    const int dz = ngp(n.cz, n.oz, v.e2) - ngp(ob.cz, ob.oz, v.e2);
+    CellPos c{0, 0, 0, 0.0f, 0.0f, o.fz + (float)dz};
+    c.x = wrap_step(o.x + (ngp(n.cx, n.ox, v.e0) - ngp(ob.cx, ob.ox, v.e0)), v.n0);
+    c.y = wrap_step(o.y + (ngp(n.cy, n.oy, v.e1) - ngp(ob.cy, ob.oy, v.e1)), v.n1);
+    c.z = wrap_step(o.z + dz, v.n2);
     return c;
 }
 
@@ -612,10 +622,9 @@ __device__ __forceinline__ int chain_cls(const DevSys &S, const uint8_t *cc, uin
     return (int)clog < S.n_chains_a ? 0 : 1;
 }
 
-// Unwrapped z cell of a bead: the floor computed by locate/step for FP32
-// positions, the stored cell for cell + offset positions.
+// Unwrapped z cell of a bead, as computed by locate/step.
 __device__ __forceinline__ int zcell(const CellPos &c, const BeadF32 &) { return (int)c.fz; }
-__device__ __forceinline__ int zcell(const CellPos &, const BeadCell &b) { return b.cz; }
+__device__ __forceinline__ int zcell(const CellPos &c, const BeadCell &) { return (int)c.fz; }
 
 // Types of beads i (even) and i + 1, from one pattern word.
 __device__ __forceinline__ void pattern_pair(const DevSys &S, int cls, int i, int &t0, int &t1)

@@ -193,3 +193,33 @@ def test_ngp_cell_is_exact_quotient_for_non_dyadic_edge(orc, mode):
         expect[(k % grid) * grid * grid] += 1
     assert (O.counts[0] == expect).all()
     assert O.counts[1][0] == n and O.counts[1].sum() == n
+
+
+@pytest.mark.parametrize("box", [2.0, 2.04])
+def test_cell_offset_window_after_trial_moves(orc, box):
+    """Cell + offset state after trial moves: every offset lies in the
+    window [-e, 2e) and some lie outside [0, e) (cells step only when an
+    offset leaves the window), and the density of the stored pairs is the
+    NGP histogram of floor(x / e) of the points x = c e + o, evaluated with
+    exact rational arithmetic (edge 0.25, and 2.04 / 8 = 0.255 rounded to
+    FP32, which is not a power of two)."""
+    from fractions import Fraction
+    s = W.diblock_system(64, 16, 0.5, 0.0, 0.0, (box, box, box), (8, 8, 8), move_halfwidth=0.2)
+    O = orc.OracleSystem(s, mode=2)
+    O.set_positions(W.gaussian_walks(s, seed=13))
+    O.run(seed=3, first_sweep=0, n_sweeps=60)
+    e32 = np.float32(box / 8)
+    assert (O.off >= -e32).all() and (O.off < 2 * e32).all()
+    assert ((O.off < 0) | (O.off >= e32)).mean() > 0.2
+    e = Fraction(float(e32))
+    n = 8
+    types = s.bead_types()
+    expect = np.zeros((2, n ** 3), np.int64)
+    for b in range(s.n_beads):
+        idx = []
+        for a in range(3):
+            x = Fraction(int(O.cell[a, b])) * e + Fraction(float(O.off[a, b]))
+            idx.append(math.floor(x / e) % n)
+        expect[types[b], (idx[0] * n + idx[1]) * n + idx[2]] += 1
+    O.density()
+    assert (O.counts == expect).all()
