@@ -1190,16 +1190,16 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
                         has1 && ((acc1 && nc1 != old1) || u1 != t1), c1, f1, t1, u1, acc0, acc1, active && bad);
 }
 
-// The sweep kernel: one launch per sweep for every system.  Wave w of the
-// grid moves the contiguous tile range [w T / W, (w+1) T / W) (T tiles, W
-// waves): with W = T (the default) one tile per wave; with fewer waves each
-// wave stays resident and walks its range.  One tile's state is live at a
+// The sweep kernel: one launch per sweep for every system.  With one tile
+// per wave (the default) wave w moves tile w; with a resident grid (fewer
+// waves) the waves walk the tiles grid-stride, each prefetching its next
+// tile's positions.  One tile's state is live at a
 // time, which keeps the register count (and so the occupancy) of the
 // one-tile case.  With FI every thread also folds count words of the
 // previous sweep: the first word's loads are issued before the move work
 // and its stores after it, so they overlap.
 template <int R, int CW, bool LOOP, int DM, bool SMC, bool CPL, bool BT>
-__global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
+__device__ __forceinline__ void sweep_body(const SweepArgs &a)
 {
     using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
     constexpr bool FI = DM == 1;
@@ -1290,6 +1290,22 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
         const int64_t n4 = 3 * W / 4, nthreads = (int64_t)gridDim.x * blockDim.x;
         for (int64_t i = gtid; i < n4; i += nthreads) fn[i] = make_uint4(0u, 0u, 0u, 0u);
     }
+}
+
+template <int R, int CW, bool LOOP, int DM, bool SMC, bool CPL, bool BT>
+__global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
+{
+    sweep_body<R, CW, LOOP, DM, SMC, CPL, BT>(a);
+}
+
+// The plain one-tile-per-wave sweep (uniform moves, no coupling) fits in 64
+// VGPRs: it asks for eight waves per SIMD, the most a SIMD holds (the SGPRs
+// beyond that budget live in VGPR lanes).  The sweep waits on memory, and
+// the eighth wave hides enough of it to pay for those moves.
+template <int R, int CW, int DM>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sweep_plain(SweepArgs a)
+{
+    sweep_body<R, CW, false, DM, false, false, false>(a);
 }
 
 // Density mode 2: counts += divergence of the face fluxes of sweep s, per
@@ -2102,6 +2118,7 @@ static void launch_sweep_d(const SweepArgs &a, int blocks, hipStream_t st)
     } else {
         if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, false, false>), g, b, lds, st, a);
         else if (a.packed) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, true>), g, b, lds, st, a);
+        else if (!SMC) hipLaunchKernelGGL((k_sweep_plain<R, CW, DM>), g, b, lds, st, a);
         else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, false>), g, b, lds, st, a);
     }
 }
