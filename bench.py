@@ -30,9 +30,12 @@ Roofline: algorithmic bytes per bead move from the hot-path scope table
 read and field write: 36 B for FP32 positions with packed uint16 counts, 60 B
 for cell + offset with uint16, 64 B for cell + offset with uint32) times the
 beads of one sweep, divided by the sweep's duration (HIP events on the
-context stream; a sweep is the sweep kernel plus, in density modes 0 and 2,
-its fold kernel).  The per-kernel split is measured with HIP events around
-each launch (soma_time_kernels) after the timed runs.
+context stream; a sweep is the sweep kernel plus its count upkeep: the fold
+kernel in density modes 0 and 2, the copy and its check in mode 3).  The
+per-kernel split is measured with HIP events around each launch
+(soma_time_kernels) after the timed runs; the HBM traffic of a sweep comes
+from the committed rocprofv3 counters (profiles/sweep_<workload>_*), reported
+only while they describe the current kernel source and density mode.
 
 The CPU baseline is the FP64 oracle (test infrastructure), timed on a
 bounded sample of the headline workload on the host cores.
@@ -169,8 +172,12 @@ def roofline_of(res, prof=None):
     r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
          "frac": achieved / HBM_PEAK_GBS,
          "traffic": prof["traffic_bytes_per_sweep"] if prof else None,
+        "traffic_source": ("rocprofv3 FETCH_SIZE x %.3f + WRITE_SIZE x %.3f of every sweep kernel, per sweep "
+                           "(profiles/sweep_%s_counters.md)" % (prof["fetch_scale"], prof["write_scale"], res["workload"]))
+        if prof else "no profile of the current kernel source and density mode",
          "bytes_per_move": bpm, "bytes_per_sweep": per_sweep,
-         "launch": "one sweep: k_sweep, plus the fold kernel in density modes 0 and 2",
+         "launch": "one sweep: the sweep kernel, then the count upkeep (fold in density modes 0 and 2, "
+                  "copy and check in mode 3)",
          "sweep_us_hip_events": res["sweep_us"],
          "library_model_bytes_per_sweep": res["info"]["bytes_per_sweep"]}
     if "kernel_us" in res:
@@ -183,10 +190,11 @@ def roofline_of(res, prof=None):
 
 def profiled(workload, density_mode):
     """The committed rocprofv3 counter summary of the sweep kernels (HBM bytes
-    and atomics per sweep), only while the kernel source is the one that was
-    profiled and the density mode matches (else None)."""
+    and atomics per sweep, profiles/sweep_<workload>_traffic.json), only while
+    the kernel source is the one that was profiled and the density mode
+    matches (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_sweep_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"sweep_{workload}_traffic.json")
     src = os.path.join(ROOT, "paper_2606_09356_amd", "csrc", "soma_kernels.hip")
     if not os.path.exists(path):
         return None
@@ -343,7 +351,7 @@ def main():
         atom.update({"atomics_per_sweep": prof["atomics_per_sweep"],
                      "achieved_per_s": prof["atomics_per_sweep"] / kern_s,
                      "frac": prof["atomics_per_sweep"] / kern_s / peak_atomics,
-                     "source": "TCC_ATOMIC_sum and k_sweep duration from the committed rocprofv3 summary"})
+                     "source": "TCC_ATOMIC_sum and the sweep kernel's duration from the committed rocprofv3 summary"})
     out["roofline"]["atomics"] = atom
 
     if not args.no_plain and args.workload in ("batched_mixed", "batched_uneven"):
