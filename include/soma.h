@@ -151,12 +151,20 @@ typedef struct {
     int32_t coupling;          /* nonzero: reserve workspace for target concentration fields
                                   (soma_place_from_fields, soma_set_umbrella): 8 B per cell
                                   plus 16 B per cell of the largest system */
-    int32_t packed_tiles;      /* 1: each workgroup moves floor(64 W / P) whole chains packed over
-                                  its W waves (P = ceil(N/2) lanes per chain), so fewer lanes
-                                  idle when 64 is not a multiple of P; chains spanning two waves
-                                  exchange their boundary beads through LDS.  Needs
-                                  waves_per_cu = 0 and no conversion zones. 0: G = floor(64/P)
-                                  chains per wave */
+    int32_t packed_tiles;      /* 0: G = floor(64/P) whole chains per wave (P = ceil(N/2) lanes
+                                  per chain).
+                                  1: each workgroup moves floor(64 W / P) whole chains packed
+                                  over its W waves, so fewer lanes idle when 64 is not a
+                                  multiple of P; chains spanning two waves exchange their
+                                  boundary beads through LDS.  No conversion zones.
+                                  2: stream tiles: a system's lanes in chain order cut into
+                                  waves of 64, so chains cross wave boundaries and no lane
+                                  idles but in a system's last wave; a wave loads the bead
+                                  before its first lane and repeats the even move of the bead
+                                  after its last lane (same decision as that bead's own
+                                  wave).  Uniform moves without walls, zones, umbrella or
+                                  caller-set classes (otherwise the sweep takes wave tiles).
+                                  1 and 2 need waves_per_cu = 0. */
 } soma_options;
 
 typedef struct {
@@ -183,7 +191,7 @@ typedef struct {
     int32_t waves_per_block;   /* launch shape in use (see soma_autotune) */
     int32_t waves_per_cu;
     int32_t xcd_remap;
-    int32_t packed_tiles;      /* sweep launched over block tiles */
+    int32_t packed_tiles;      /* tiling in use: 0 wave tiles, 1 block tiles, 2 stream tiles */
 } soma_info;
 
 /* Bytes of device workspace that soma_create needs for these systems. */

@@ -58,6 +58,7 @@ struct Layout {
         ptiles, total;   // base: counts, delta: density delta; ptiles: block tiles
     int64_t total_slots = 0, total_cells = 0, total_chains = 0, count_words = 0, total_beads = 0;
     int n_tiles = 0;
+    int n_ptiles_cap = 0;   // entries of the block/stream tile table
     int n_chunks = 0;      // fold chunks of density mode 2
     int64_t max_obs_blocks = 0, max_cells = 0;
 };
@@ -192,9 +193,9 @@ int validate(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt
     if (opt->density_mode < 0 || opt->density_mode > 3) { msg = "density_mode must be 0, 1, 2 or 3"; return SOMA_EINVAL; }
     if (opt->reorder_every < 0) { msg = "reorder_every must be >= 0"; return SOMA_EINVAL; }
     if (opt->launch_order != 0 && opt->launch_order != 1) { msg = "launch_order must be 0 or 1"; return SOMA_EINVAL; }
-    if (opt->packed_tiles != 0 && opt->packed_tiles != 1) { msg = "packed_tiles must be 0 or 1"; return SOMA_EINVAL; }
+    if (opt->packed_tiles < 0 || opt->packed_tiles > 2) { msg = "packed_tiles must be 0, 1 or 2"; return SOMA_EINVAL; }
     if (opt->packed_tiles && opt->waves_per_cu > 0) { msg = "packed_tiles needs waves_per_cu = 0"; return SOMA_EINVAL; }
-    for (int32_t k = 0; k < n_sys && opt->packed_tiles; ++k)
+    for (int32_t k = 0; k < n_sys && opt->packed_tiles == 1; ++k)
         if (sys[k].zones[0] > 0 || sys[k].zones[1] > 0) { msg = "packed_tiles is not available with conversion zones"; return SOMA_EINVAL; }
     if (opt->sys_id_base < 0 || (int64_t)opt->sys_id_base + n_sys >= (int64_t(1) << 31)) { msg = "sys_id_base + n_sys must stay below 2^31"; return SOMA_EINVAL; }
     for (int32_t k = 0; k < n_sys; ++k) {
@@ -253,7 +254,7 @@ void set_field_coefs(HostSys &h);
 Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt, std::vector<HostSys> *out)
 {
     Layout L{};
-    int64_t slots = 0, cells = 0, chains = 0, beads = 0;
+    int64_t slots = 0, cells = 0, chains = 0, beads = 0, stiles = 0;
     int tiles = 0;
     int64_t max_blocks = 1, max_cells = 1;
     for (int32_t k = 0; k < n_sys; ++k) {
@@ -328,6 +329,7 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
         chains += d.n_chains;
         beads += (int64_t)d.n_chains * d.N;
         tiles += nt;
+        stiles += ((int64_t)d.n_chains * P + soma::kStreamLanes - 1) / soma::kStreamLanes;
         max_blocks = std::max<int64_t>(max_blocks, (d.n_chains + 255) / 256 + (M + 255) / 256);
         max_cells = std::max<int64_t>(max_cells, M);
     }
@@ -344,7 +346,9 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     L.systems = take(sizeof(DevSys) * n_sys);
     L.tiles = take(sizeof(Tile) * tiles);
-    L.ptiles = take(sizeof(Tile) * tiles);     // block tiles never outnumber wave tiles
+    // block tiles never outnumber wave tiles; stream tiles may, by a few
+    L.ptiles = take(sizeof(Tile) * (size_t)std::max<int64_t>(tiles, stiles));
+    L.n_ptiles_cap = (int)std::max<int64_t>(tiles, stiles);
     L.chain_id = take(sizeof(uint32_t) * chains);
     L.chain_id2 = take(sizeof(uint32_t) * chains);
     for (int a = 0; a < 3; ++a) L.P[a] = take(sizeof(float) * slots);
@@ -417,27 +421,47 @@ int sync_status(soma_ctx *c)
 
 // Launch shape of the sweep kernel: waves per workgroup, resident grid
 // (waves per compute unit, 0 for one tile per wave) and block order.
+int any_coupling(const soma_ctx *c);
+
+// packed: 1 block tiles (not with conversion zones), 2 stream tiles (uniform
+// moves without coupling; a context that gains coupling later sweeps over
+// wave tiles, see launch_sweep); both only with one tile per wave.
 void set_shape(soma_ctx *c, int waves_per_block, int waves_per_cu, int xcd_remap, int packed = 0)
 {
     c->waves_per_block = waves_per_block;
     c->waves_per_cu = waves_per_cu;
     c->xcd_remap = xcd_remap;
     c->max_blocks = waves_per_cu > 0 ? std::max(1, waves_per_cu * c->n_cus / waves_per_block) : 0;
-    c->packed = packed && waves_per_cu == 0 && !c->any_zones ? 1 : 0;
+    if (packed == 2)
+        c->packed = waves_per_cu == 0 && !c->any_smc && !any_coupling(c) ? 2 : 0;
+    else
+        c->packed = packed && waves_per_cu == 0 && !c->any_zones ? 1 : 0;
 }
 
 // Block tiles for the current waves per block: floor(64 W / P) whole chains
-// of one system per tile.  Uploaded before the next sweep launch.
+// of one system per tile.  Stream tiles: the lanes of a system (P per chain)
+// in runs of 62 owned lanes per wave; a tile names its system (low 24 bits),
+// the pair index of its first owned lane within that lane's chain (high 8
+// bits) and that chain.  Uploaded before the next sweep launch.
 int upload_block_tiles(soma_ctx *c)
 {
     if (!c->packed) return SOMA_OK;
     std::vector<Tile> t;
-    const int lanes = 64 * c->waves_per_block;
-    for (size_t k = 0; k < c->sys.size(); ++k) {
-        const int Gw = lanes / c->sys[k].dev.P;
-        for (int ch = 0; ch < c->sys[k].d.n_chains; ch += Gw) t.push_back(Tile{(uint32_t)k, (uint32_t)ch});
+    if (c->packed == 2) {
+        if (c->sys.size() >= (size_t(1) << 24)) return fail(c, SOMA_EINVAL, "stream tiles hold at most 2^24 systems");
+        for (size_t k = 0; k < c->sys.size(); ++k) {
+            const int64_t P = c->sys[k].dev.P, lanes = (int64_t)c->sys[k].d.n_chains * P;
+            for (int64_t l = 0; l < lanes; l += soma::kStreamLanes)
+                t.push_back(Tile{(uint32_t)k | ((uint32_t)(l % P) << 24), (uint32_t)(l / P)});
+        }
+    } else {
+        const int lanes = 64 * c->waves_per_block;
+        for (size_t k = 0; k < c->sys.size(); ++k) {
+            const int Gw = lanes / c->sys[k].dev.P;
+            for (int ch = 0; ch < c->sys[k].d.n_chains; ch += Gw) t.push_back(Tile{(uint32_t)k, (uint32_t)ch});
+        }
     }
-    if ((int)t.size() > c->L.n_tiles) return fail(c, SOMA_EDEVICE, "block tile table overflow");
+    if ((int64_t)t.size() > c->L.n_ptiles_cap) return fail(c, SOMA_EDEVICE, "block tile table overflow");
     if (t.size() == c->ptiles_host.size() && c->n_ptiles == (int)t.size() &&
         std::equal(t.begin(), t.end(), c->ptiles_host.begin(),
                    [](const Tile &x, const Tile &y) { return x.sys == y.sys && x.chain0 == y.chain0; }))
@@ -1638,16 +1662,18 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
                     best.us_per_sweep_before);
     best.us_per_sweep = best.us_per_sweep_before;
     // wave tiles: one per wave, or resident grids of 8 or 32 waves per CU;
-    // block tiles (-1 here): one per block
-    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32, -1}, kXcd[] = {1, 0}, kDm[] = {0, 1, 2, 3};
+    // block tiles (-1 here): one per block; stream tiles (-2): one per wave
+    static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32, -1, -2}, kXcd[] = {1, 0}, kDm[] = {0, 1, 2, 3};
+    const bool stream_ok = !c->any_smc && !any_coupling(c);
     for (int dm : kDm)
         for (int wpb : kWpb)
             for (int wpcu : kWpcu)
                 for (int xcd : kXcd) {
                     if (rc != SOMA_OK) break;
                     if (dm == 2 && c->any_zones) continue;   // conversions need cell words
-                    if (wpcu < 0 && (c->any_zones || wpb == 1)) continue;   // one wave: the same tiles
-                    const int pk = wpcu < 0 ? 1 : 0, cu = wpcu < 0 ? 0 : wpcu;
+                    if (wpcu == -1 && (c->any_zones || wpb == 1)) continue;   // one wave: the same tiles
+                    if (wpcu == -2 && !stream_ok) continue;
+                    const int pk = wpcu == -1 ? 1 : (wpcu == -2 ? 2 : 0), cu = wpcu < 0 ? 0 : wpcu;
                     double us = 0.0;
                     rc = time_shape(wpb, cu, xcd, dm, pk, us);
                     ++best.n_candidates;

@@ -980,6 +980,147 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
 }
 
 // ---------------------------------------------------------------------------
+// Stream tiles (uniform moves, no coupling)
+// ---------------------------------------------------------------------------
+// The lanes of a system form one stream in chain order (chain c holds lanes
+// [c P, (c + 1) P)), so chains run across wave boundaries and no lane idles
+// but in a system's last wave.  Wave w moves the 62 stream lanes
+// [62 w, 62 w + 62) on its lanes 1..62; lane 0 holds the stream lane before
+// them and lane 63 the one after, which take every step of the sweep but
+// store nothing, update no count and count no acceptance.  Lane 1's even
+// bead reads lane 0's odd bead (unmoved in the even pass), and lane 62's odd
+// bead reads lane 63's even bead after lane 63 has made that bead's even move
+// with the same draw, stored state, frozen counts and arithmetic as the wave
+// that owns it, so the same decision.  A stream tile names its system (low
+// 24 bits), the pair index of its first owned lane within that lane's chain
+// (high 8 bits) and that chain.
+__device__ __forceinline__ uint32_t stile_sys(const Tile &T) { return T.sys & 0xFFFFFFu; }
+
+struct StreamLane {
+    int chain, p;
+    bool valid;     // a bead pair of the system: takes every step
+    bool own;       // and belongs to this wave: stores and counts
+};
+
+__device__ __forceinline__ StreamLane stream_lane(const Tile &T, const DevSys &S)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int P = S.P;
+    // stream lane 62 w - 1 + lane, as (chain0 - 1 + gr, q - gr P) with q >= 0
+    const int q = (int)(T.sys >> 24) + lane - 1 + P;            // < 2 P + 63
+    const int gr = (int)(((float)q + 0.5f) * S.inv_P);
+    StreamLane L;
+    L.chain = (int)T.chain0 - 1 + gr;
+    L.p = q - gr * P;
+    L.valid = L.chain >= 0 && L.chain < S.n_chains;
+    L.own = L.valid && lane >= 1 && lane <= kStreamLanes;
+    return L;
+}
+
+template <class Bead>
+__device__ __forceinline__ void stream_load(const SweepArgs &a, int tile, Bead &b0, Bead &b1, uint32_t &clog)
+{
+    const Tile T = a.ptiles[tile];
+    const DevSys &S = a.systems[stile_sys(T)];
+    const StreamLane L = stream_lane(T, S);
+    clog = a.chain_id[S.chain_off + (L.valid ? L.chain : (int)T.chain0)];
+    b0 = Bead{};
+    b1 = Bead{};
+    if (L.valid)
+        load_pair(PosArrays{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2}, S.slot_off + (int64_t)L.chain * (2 * S.P) + 2 * L.p,
+                  b0, b1);
+}
+
+template <int R, int CW, int DM, class Bead>
+__device__ __forceinline__ void sweep_tile_stream(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
+                                                  const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
+                                                  uint32_t *agg_vals, Bead b0, Bead b1, uint32_t clog)
+{
+    const Tile T = a.ptiles[wave];
+    const uint32_t sys = stile_sys(T);
+    const DevSys &S = a.systems[sys];
+    const SysView v = make_view(S);
+    const FieldCoef fc{S.cAA, S.cAB, S.cBA, S.cBB, S.c0};
+    const bool frozen = S.frozen != 0;
+    const int64_t cell_off = S.cell_off;
+    const int N = S.N, P = S.P;
+    const StreamLane L = stream_lane(T, S);
+    const bool valid = L.valid, own = L.own;
+    const int p = L.p;
+    const int i0 = 2 * p, i1 = 2 * p + 1;
+    const bool has1 = valid && i1 < N;
+    const int64_t slot = S.slot_off + (int64_t)(valid ? L.chain : 0) * (2 * P) + 2 * p;
+    const PosArrays A{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2};
+    const Bead ob0 = b0, ob1 = b1;
+
+    const int cls = chain_cls<false>(S, a.chain_class, clog);
+    int t0, t1;
+    pattern_pair(S, cls, i0, t0, t1);
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const float delta_s = S.delta * 0x1p-23f;
+    const Draw d0 = move_draw((uint32_t)i0, clog, (uint32_t)s, S.sys_id, k0, k1, delta_s);
+    const Draw d1 = move_draw((uint32_t)i1, clog, (uint32_t)s, S.sys_id, k0, k1, delta_s);
+    bool bad = false;
+    const CellPos c0 = locate(b0, v, bad);
+    const CellPos c1 = locate(b1, v, bad);
+    const int old0 = lin(c0, v), old1 = lin(c1, v);
+    const Bead n0 = propose(b0, d0, v);
+    const Bead n1 = propose(b1, d1, v);
+    const CellPos s0 = step(c0, b0, n0, v), s1 = step(c1, b1, n1, v);
+    const int nc0 = lin(s0, v), nc1 = lin(s1, v);
+    const bool g0 = valid && nc0 != old0, g1 = has1 && nc1 != old1;
+    float dw0 = 0.0f, dw1 = 0.0f;
+    if (frozen) {
+        float2 wn0{0.f, 0.f}, wo0{0.f, 0.f}, wn1{0.f, 0.f}, wo1{0.f, 0.f};
+        if (g0) { wn0 = a.omega[cell_off + nc0]; wo0 = a.omega[cell_off + old0]; }
+        if (g1) { wn1 = a.omega[cell_off + nc1]; wo1 = a.omega[cell_off + old1]; }
+        dw0 = t0 ? wn0.y - wo0.y : wn0.x - wo0.x;
+        dw1 = t1 ? wn1.y - wo1.y : wn1.x - wo1.x;
+    } else {
+        RawCount rn0{0u, 0u, 0u, 0u}, ro0{0u, 0u, 0u, 0u}, rn1{0u, 0u, 0u, 0u}, ro1{0u, 0u, 0u, 0u};
+        if (g0) {
+            rn0 = load_raw<CW, DM == 1>(cin, dprev, cell_off + nc0);
+            ro0 = load_raw<CW, DM == 1>(cin, dprev, cell_off + old0);
+        }
+        if (g1) {
+            rn1 = load_raw<CW, DM == 1>(cin, dprev, cell_off + nc1);
+            ro1 = load_raw<CW, DM == 1>(cin, dprev, cell_off + old1);
+        }
+        if (g0) dw0 = omega_of(fc, counts_of<CW>(rn0), t0) - omega_of(fc, counts_of<CW>(ro0), t0);
+        if (g1) dw1 = omega_of(fc, counts_of<CW>(rn1), t1) - omega_of(fc, counts_of<CW>(ro1), t1);
+    }
+    const float kh = S.k_half;
+    const float3 zero = make_float3(0.0f, 0.0f, 0.0f);
+
+    // even pass: bead 2p, neighbours 2p-1 (previous lane) and 2p+1
+    bool acc0;
+    {
+        const Bead left = left_neighbour<false>(b1);
+        const float3 de = bond(n0, b0, v);
+        const float3 bl = p > 0 ? bond(b0, left, v) : zero, br = i1 < N ? bond(b0, b1, v) : zero;
+        const float nj = (p > 0 ? 1.0f : 0.0f) + (i1 < N ? 1.0f : 0.0f);
+        const float dE = fmaf(fmaf(2.0f, dot3(de, add3(bl, br)), nj * dot3(de, de)), kh, dw0);
+        acc0 = valid && (d0.u < __expf(-dE));
+        if (acc0) b0 = n0;
+    }
+    // odd pass: bead 2p+1, neighbours 2p (this lane, updated) and 2p+2 (next lane)
+    bool acc1;
+    {
+        const Bead right = right_neighbour<false>(b0);
+        const float3 de = bond(n1, b1, v);
+        const float3 br = i1 + 1 < N ? bond(b1, right, v) : zero;
+        const float nj = i1 + 1 < N ? 2.0f : 1.0f;
+        const float dE = fmaf(fmaf(2.0f, dot3(de, add3(bond(b1, b0, v), br)), nj * dot3(de, de)), kh, dw1);
+        acc1 = has1 && (d1.u < __expf(-dE));
+        if (acc1) b1 = n1;
+    }
+    const bool own1 = own && has1;
+    if (own) store_moved(A, slot, b0, b1, ob0, ob1, acc0 || acc1);
+    tile_finish<CW, DM>(a, wave, sys, cell_off, v, dcur, agg_keys, agg_vals, own && acc0 && nc0 != old0, c0, s0, t0,
+                        t0, own1 && acc1 && nc1 != old1, c1, s1, t1, t1, own && acc0, own1 && acc1, own && bad);
+}
+
+// ---------------------------------------------------------------------------
 // Bond-force-biased ("smart") moves (Sec. 2; Rossky, Doll and Friedman 1978)
 // ---------------------------------------------------------------------------
 // Three standard normals by Box-Muller (FP64) on the Philox block with counter
@@ -1198,7 +1339,7 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
 // one-tile case.  With FI every thread also folds count words of the
 // previous sweep: the first word's loads are issued before the move work
 // and its stores after it, so they overlap.
-template <int R, int CW, bool LOOP, int DM, bool SMC, bool CPL, bool BT>
+template <int R, int CW, bool LOOP, int DM, bool SMC, bool CPL, bool BT, bool ST = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a)
 {
     using Bead = typename std::conditional<R == REPR_F32, BeadF32, BeadCell>::type;
@@ -1253,7 +1394,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     } else {
         // block tiles: the test is uniform over the block, so every thread
         // of a working block reaches the barriers of the tile
-        if (wave < (BT ? a.n_ptiles : a.n_tiles)) {
+        if constexpr (ST) {
+            if (wave < a.n_ptiles) {
+                Bead b0, b1;
+                uint32_t clog;
+                stream_load(a, wave, b0, b1, clog);
+                agg_clear<SLOTS>(agg_keys, agg_vals);
+                sweep_tile_stream<R, CW, DM>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog);
+            }
+        } else if (wave < (BT ? a.n_ptiles : a.n_tiles)) {
             Bead b0, b1;
             uint32_t clog;
             tile_load<BT>(a, wave, b0, b1, clog);
@@ -1305,7 +1454,14 @@ __global__ __launch_bounds__(1024) void k_sweep(SweepArgs a)
 template <int R, int CW, int DM>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sweep_plain(SweepArgs a)
 {
-    sweep_body<R, CW, false, DM, false, false, false>(a);
+    sweep_body<R, CW, false, DM, false, false, false, false>(a);
+}
+
+// Stream tiles, with the same register budget.
+template <int R, int CW, int DM>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sweep_stream(SweepArgs a)
+{
+    sweep_body<R, CW, false, DM, false, false, false, true>(a);
 }
 
 // Density mode 2: counts += divergence of the face fluxes of sweep s, per
@@ -2113,11 +2269,12 @@ static void launch_sweep_d(const SweepArgs &a, int blocks, hipStream_t st)
     // chain sums stay within a wave)
     if (a.cpl) {
         if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, true, false>), g, b, lds, st, a);
-        else if (a.packed) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true, true>), g, b, lds, st, a);
+        else if (a.packed == 1) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true, true>), g, b, lds, st, a);
         else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true, false>), g, b, lds, st, a);
     } else {
         if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, false, false>), g, b, lds, st, a);
-        else if (a.packed) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, true>), g, b, lds, st, a);
+        else if (a.packed == 1) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, true>), g, b, lds, st, a);
+        else if (!SMC && a.packed == 2) hipLaunchKernelGGL((k_sweep_stream<R, CW, DM>), g, b, lds, st, a);
         else if (!SMC) hipLaunchKernelGGL((k_sweep_plain<R, CW, DM>), g, b, lds, st, a);
         else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, false>), g, b, lds, st, a);
     }
@@ -2145,7 +2302,11 @@ hipError_t launch_sweep(int repr, int cw, const SweepArgs &a, hipStream_t st)
 {
     int blocks = (a.n_tiles + a.waves_per_block - 1) / a.waves_per_block;
     if (a.max_blocks > 0 && blocks > a.max_blocks) blocks = a.max_blocks;
-    if (a.packed && a.max_blocks == 0) blocks = a.n_ptiles;
+    if (a.packed == 1 && a.max_blocks == 0) blocks = a.n_ptiles;
+    // stream tiles only for uniform moves without coupling (the launch below
+    // takes wave tiles otherwise)
+    if (a.packed == 2 && a.max_blocks == 0 && !a.cpl && !a.smc)
+        blocks = (a.n_ptiles + a.waves_per_block - 1) / a.waves_per_block;
     if (blocks <= 0) return hipErrorInvalidConfiguration;   // the tile tables are empty
     if (repr == REPR_F32)
         return cw == COUNT_U16 ? launch_sweep_t<REPR_F32, COUNT_U16>(a, blocks, st)

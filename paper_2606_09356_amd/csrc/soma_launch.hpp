@@ -7,13 +7,18 @@
 
 namespace soma {
 
+// Stream tiles: owned lanes per wave (lanes 1..62; lanes 0 and 63 hold the
+// neighbouring stream lanes).
+constexpr int kStreamLanes = 62;
+
 struct SweepArgs {
     const DevSys *systems;
     const Tile *tiles;
     int n_tiles;
     const Tile *ptiles;            // block tiles (chains packed over the waves of a block)
     int n_ptiles;
-    int packed;                    // 1: one block tile per block (only with max_blocks == 0)
+    int packed;                    // 1: one block tile per block; 2: stream tiles, one per wave
+                                   // (only with max_blocks == 0)
     int waves_per_block;
     int max_blocks;                // 0: one tile per wave; else the grid size (waves loop over tiles)
     int xcd_remap;

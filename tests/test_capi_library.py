@@ -76,7 +76,7 @@ def test_invalid_options_are_rejected(lib):
     n = C.c_size_t(0)
     for kw in [dict(pos_repr=3), dict(count_width=7), dict(waves_per_block=17), dict(density_mode=4),
                dict(density_mode=-1), dict(sys_id_base=-1), dict(launch_order=2), dict(waves_per_cu=65),
-               dict(packed_tiles=2), dict(packed_tiles=1, waves_per_cu=8)]:
+               dict(packed_tiles=3), dict(packed_tiles=1, waves_per_cu=8), dict(packed_tiles=2, waves_per_cu=8)]:
         assert lib.soma_workspace_size(arr, 1, C.byref(_opts(**kw)), C.byref(n)) == S.SOMA_EINVAL, kw
 
 

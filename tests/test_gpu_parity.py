@@ -130,7 +130,7 @@ def test_fields_match_oracle(name):
 
 
 @pytest.mark.parametrize("reorder,dm,pk", [(0, 0, 0), (1, 0, 0), (0, 2, 0), (1, 1, 0), (0, 0, 1), (1, 2, 1),
-                                           (0, 3, 0), (1, 3, 1)])
+                                           (0, 3, 0), (1, 3, 1), (1, 3, 2), (0, 2, 2), (1, 1, 2)])
 @pytest.mark.parametrize("name", list(small_cases()))
 def test_single_and_multi_sweep_parity(name, reorder, dm, pk):
     systems, r, cw = small_cases()[name]
@@ -153,6 +153,67 @@ def test_single_and_multi_sweep_parity(name, reorder, dm, pk):
     print(f"[{name}] {mism} differing beads of {total}")
     assert mism <= max(1, int(1e-6 * total)), (mism, total)
     g.close()
+
+
+def stream_systems():
+    """Chains that cross wave boundaries in stream tiles: P = ceil(N/2) lanes
+    per chain does not divide 64 (odd and even N, 33..63 lanes, and short
+    chains), with chiN > 0 so the field term decides moves too."""
+    out = []
+    for k, (N, nch) in enumerate([(67, 300), (100, 200), (125, 160), (9, 2000), (2, 5000), (41, 500)]):
+        box = round((N * nch / 128.0) ** (1.0 / 3.0) * 4) / 4
+        n = int(box * 4)
+        out.append(W.diblock_system(nch, N, 0.4 + 0.05 * k, 15.0 + 3 * k, 50.0, (box, box, box), (n, n, n), f"stream{k}"))
+    return out
+
+
+@pytest.mark.parametrize("r,cw,dm", [("cell", 16, 3), ("f32", 16, 0), ("cell", 32, 1), ("f32", 16, 2)])
+def test_stream_tile_parity(r, cw, dm):
+    """Stream tiles: every decision of three sweeps equals the oracle's and
+    the density is bit-exact, on chains that cross wave boundaries (the
+    wave repeats the even move of the bead after its last lane); the same
+    context in wave tiles runs the identical trajectory."""
+    systems = stream_systems()
+    g, orcs = make_pair(systems, r, cw, density_mode=dm, packed_tiles=2, waves_per_block=4)
+    assert g.info()["packed_tiles"] == 2
+    h = Soma(systems, seed=SEED, pos_repr=r, count_width=cw, density_mode=dm)
+    for k, s in enumerate(systems):
+        h.set_positions(k, W.gaussian_walks(s, seed=7 + k))
+    total = mism = 0
+    for sweep in range(3):
+        g.sweep(1)
+        h.sweep(1)
+        for k, o in enumerate(orcs):
+            o.sweep(SEED, sweep)
+            o.density()
+            o.fields()
+            eq = same_state(g, k, o)
+            total += eq.size
+            mism += int((~eq).sum())
+            assert (g.density(k) == oracle_density_of_gpu_state(g, k, o)).all()
+            assert _same_state(g.state(k), h.state(k)), (k, sweep)
+    print(f"[stream {r}/u{cw}/dm{dm}] {mism} differing beads of {total}")
+    assert mism <= max(1, int(1e-6 * total)), (mism, total)
+    for k in range(len(systems)):
+        assert g.observables(k)["n_accepted"] == h.observables(k)["n_accepted"]
+    g.close()
+    h.close()
+
+
+def test_stream_tiles_fall_back_with_smart_moves():
+    """Stream tiles are asked for but the context moves with smart moves: the
+    shape reports wave tiles and the sweep matches a wave-tile context."""
+    systems = stream_systems()[:2]
+    systems[0].smc_A = 0.001
+    g = Soma(systems, seed=SEED, pos_repr="f32", count_width=16, packed_tiles=2)
+    h = Soma(systems, seed=SEED, pos_repr="f32", count_width=16)
+    assert g.info()["packed_tiles"] == 0
+    g.sweep(2)
+    h.sweep(2)
+    for k in range(len(systems)):
+        assert _same_state(g.state(k), h.state(k))
+    g.close()
+    h.close()
 
 
 def test_accept_counter_matches_oracle():
@@ -249,7 +310,7 @@ def test_autotune_keeps_the_trajectory(r):
     b.sweep(2)
     t = a.autotune(trial_sweeps=2)
     print(f"[autotune {r}] {t}", flush=True)
-    assert t["n_candidates"] == 152 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
+    assert t["n_candidates"] == 192 and 0 < t["us_per_sweep"] and 0 < t["us_per_sweep_before"]
     i = a.info()
     assert (i["waves_per_block"], i["waves_per_cu"], i["xcd_remap"], i["density_mode"], i["packed_tiles"]) == \
         (t["waves_per_block"], t["waves_per_cu"], t["xcd_remap"], t["density_mode"], t["packed_tiles"])
@@ -451,7 +512,7 @@ def apply_shape(g, shape):
     return g
 
 
-@pytest.mark.parametrize("shape", ["auto", "dm0", "dm1", "dm2", "dm3"])
+@pytest.mark.parametrize("shape", ["auto", "dm0", "dm1", "dm2", "dm3", "stream"])
 @pytest.mark.parametrize("name", ["plain_large", "mixed_large"])
 def test_full_size_single_sweep_parity(name, shape):
     """Full-size workloads, in the benchmark's launch configuration (the
@@ -463,9 +524,9 @@ def test_full_size_single_sweep_parity(name, shape):
     s = systems[0]
     print(f"[full-size] {name} ({shape}): {s.n_beads} beads", flush=True)
     xyz = W.gaussian_walks(s, seed=11)
-    dm = int(shape[2]) if shape.startswith("dm") else 0
+    dm = int(shape[2]) if shape.startswith("dm") else (3 if shape == "stream" else 0)
     g = apply_shape(Soma(systems, seed=SEED, pos_repr=r, count_width=cw, density_mode=dm,
-                         reorder_every=opts["reorder_every"]), shape)
+                         packed_tiles=2 if shape == "stream" else 0, reorder_every=opts["reorder_every"]), shape)
     g.set_positions(0, xyz)
     o = oracle.OracleSystem(s, sys_id=0, mode=oracle.MODE_F32 if r == "f32" else oracle.MODE_CELL)
     o.set_positions(xyz)

@@ -153,7 +153,7 @@ def test_equilibrium_observables_agree_with_oracle():
             assert diff <= 5e-3 * abs(mo), (r, k, diff)
 
 
-@pytest.mark.parametrize("shape", ["auto", "dm1", "dm2", "dm3", "packed"])
+@pytest.mark.parametrize("shape", ["auto", "dm1", "dm2", "dm3", "packed", "stream"])
 @pytest.mark.parametrize("name,sample", [("batched_uneven", [0, 17, 63]), ("batched_mixed", [0, 101, 255])])
 def test_full_size_batched_sampled_parity(name, sample, shape):
     """One sweep of the full batched workloads in the benchmark's launch
@@ -163,8 +163,8 @@ def test_full_size_batched_sampled_parity(name, sample, shape):
     r, cw = opts["pos_repr"], opts["count_width"]
     print(f"[full-size] {name} ({shape}): {len(systems)} systems, {sum(s.n_beads for s in systems)} beads",
           flush=True)
-    dm = int(shape[2]) if shape.startswith("dm") else 0
-    pk = 1 if shape == "packed" else 0
+    dm = int(shape[2]) if shape.startswith("dm") else (3 if shape == "stream" else 0)
+    pk = {"packed": 1, "stream": 2}.get(shape, 0)
     g = Soma(systems, seed=SEED, pos_repr=r, count_width=cw, reorder_every=opts["reorder_every"], density_mode=dm,
              packed_tiles=pk, waves_per_block=4 if pk else 0)
     if shape == "auto":
