@@ -96,8 +96,9 @@ def parse():
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the default launch shape instead of timing every shape first")
     p.add_argument("--shape", default=None,
-                   help="fixed launch shape WPB,WPCU,ORDER,DM for the main workload (no autotuning): "
-                        "waves per block, waves per CU (0: one tile per wave), launch_order, density_mode")
+                   help="fixed launch shape WPB,WPCU,ORDER,DM[,PACKED] for the main workload (no "
+                        "autotuning): waves per block, waves per CU (0: one tile per wave), launch_order, "
+                        "density_mode, packed_tiles (0 wave tiles, 1 block tiles, 2 stream tiles)")
     return p.parse_args()
 
 
@@ -126,16 +127,16 @@ def timed_sweeps(g, steps, warmup, runs=RUNS):
 
 def make_context(systems, opts, shape=None, sys_id_base=0):
     from paper_2606_09356_amd.soma import Soma
-    wpb, wpcu, order, dm = shape if shape else (0, 0, 0, 0)
+    wpb, wpcu, order, dm, packed = (tuple(shape) + (0,))[:5] if shape else (0, 0, 0, 0, 0)
     return Soma(systems, seed=SEED, pos_repr=opts["pos_repr"], count_width=opts["count_width"],
                 use_graph=True, waves_per_block=wpb, waves_per_cu=wpcu, launch_order=order, density_mode=dm,
-                reorder_every=opts["reorder_every"], sys_id_base=sys_id_base)
+                reorder_every=opts["reorder_every"], sys_id_base=sys_id_base, packed_tiles=packed)
 
 
 def shape_of(info, tune=None):
     d = {"waves_per_block": info["waves_per_block"], "waves_per_cu": info["waves_per_cu"],
          "xcd_remap": info["xcd_remap"], "density_mode": info["density_mode"],
-         "autotuned": tune is not None}
+         "packed_tiles": info["packed_tiles"], "autotuned": tune is not None}
     if tune is not None:
         d["tune_from_cache"] = bool(tune.get("from_cache", 0))
     return d
@@ -284,9 +285,10 @@ def cpu_baseline(name, budget_s=15.0):
     rate = moves / busy
     return {"value": rate, "unit": "bead moves/s", "cores": cores, "kind": "oracle",
             "per_core": rate / cores, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
-            "sample": f"one full sweep (move, density, field) of each of the first {sweeps} systems of the "
-                      f"{name} workload ({moves} bead moves), {busy:.1f} s of oracle time on {cores} OpenMP "
-                      "threads (setup excluded)"}
+            "sample": f"one full sweep (move, density, field) per system, the {name} workload's "
+                      f"{len(systems)} systems taken in order and again from the first: {sweeps} system "
+                      f"sweeps, {moves} bead moves, {busy:.1f} s of oracle time on {cores} OpenMP threads "
+                      "(setup excluded)"}
 
 
 def main():
@@ -371,9 +373,10 @@ def main():
                                          "batched_over_plain": main_res["moves_per_s"] / plain["moves_per_s"],
                                          "re2": plain["re2"][0], "launch_shape": plain["launch_shape"],
                                          "roofline_frac": roofline_of(plain)["frac"]},
-            "matched_re2": "same systems alone: bit-identical Re^2 (difference above); plain FP32 form: "
-                           "its representation error (1.5e-5 relative Re^2 against FP64 positions) exceeds "
-                           "the cell form's (1.1e-10)",
+            "matched_re2": "same systems alone: the same random numbers (sys_id_base), so the same "
+                           "trajectory; re2_max_abs_diff above checks it and is 0.0 when every system's Re^2 is "
+                           "bit-identical; plain FP32 form: its representation error (1.5e-5 relative Re^2 "
+                           "against FP64 positions) exceeds the cell form's (1.1e-10)",
         }
     if not args.no_extra:
         legs = {}

@@ -157,10 +157,11 @@ typedef struct {
                                   over its W waves, so fewer lanes idle when 64 is not a
                                   multiple of P; chains spanning two waves exchange their
                                   boundary beads through LDS.  No conversion zones.
-                                  2: stream tiles: a system's lanes in chain order cut into
-                                  waves of 64, so chains cross wave boundaries and no lane
-                                  idles but in a system's last wave; a wave loads the bead
-                                  before its first lane and repeats the even move of the bead
+                                  2: stream tiles: a system's lanes in chain order, 62 owned
+                                  lanes per wave, so chains cross wave boundaries and no lane
+                                  idles but in a system's last wave; a wave also takes the
+                                  lane before and the lane after its own (from a copy made
+                                  before the sweep) and repeats the even move of the bead
                                   after its last lane (same decision as that bead's own
                                   wave).  Uniform moves without walls, zones, umbrella or
                                   caller-set classes (otherwise the sweep takes wave tiles).
@@ -344,14 +345,18 @@ int soma_get_info(soma_ctx *ctx, soma_info *out);
 /* Launch-shape autotuning, the "adjusting launch configurations" step of
  * the SOMA optimisation (Sec. 2.2).  For every candidate shape -- waves per
  * workgroup in {1, 2, 4, 8, 16}; one tile per wave, a resident grid of 8 or
- * 32 waves per compute unit walking tile ranges, or one block tile per
- * workgroup; XCD-aware block order on or off; density mode 0, 1 or 2 (not 2
- * with conversion zones) -- times `trial_sweeps` sweeps (1..1000)
- * after one warm-up sweep, and keeps the fastest for every later sweep.  The trial
- * sweeps are undone: positions, counts, acceptance counters, the status
- * word and the sweep counter are restored, so the trajectory is exactly
- * the one of an untuned context (launch shapes never change results).
- * Synchronises; out may be NULL.  SOMA_EINVAL for a bad trial count. */
+ * 32 waves per compute unit walking tile ranges, one block tile per
+ * workgroup, or stream tiles (uniform moves without coupling only);
+ * XCD-aware block order on or off; density mode 0, 1, 2 or 3 (not 2 with
+ * conversion zones) -- times `trial_sweeps` sweeps (1..1000) after a
+ * warm-up batch of as many; the four fastest are timed twice more, and the
+ * one with the lowest median of its three times is kept for every later
+ * sweep.  The trial sweeps are undone: positions, counts, acceptance
+ * counters, the status word and the sweep counter are restored, so the
+ * trajectory is exactly the one of an untuned context (launch shapes never
+ * change results).  The choice is cached per process (see
+ * soma_tune_cache_clear).  Synchronises; out may be NULL.  SOMA_EINVAL for a
+ * bad trial count. */
 typedef struct {
     int32_t waves_per_block;   /* chosen shape */
     int32_t waves_per_cu;      /* 0: one tile per wave */

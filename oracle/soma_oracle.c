@@ -16,8 +16,7 @@
  *   Sec. 2.2 (SOMA Optimization): the two dominant kernels perform trial
  *     moves with energy evaluations, and rebuild the particle density
  *     fields; bead coordinates are generated at initialisation.
- *   The paper gives no formulas for the model.  The readings used here (all
- *   stated in DESIGN.md, "Readings of the paper") are:
+ *   The paper gives no formulas for the model.  The readings used here are:
  *     bonds      harmonic, E_b/kT = (k/2) sum |r_{i+1}-r_i|^2, k = 3(N-1)/Re^2
  *     H_nb/kT    (rho0 dV / N) sum_cells f(phiA, phiB) with
  *                Helfand form  f = (kN/2)(phiA+phiB-1)^2 - (chiN/4)(phiA-phiB)^2

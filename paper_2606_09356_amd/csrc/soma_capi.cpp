@@ -52,7 +52,7 @@ double *scratch_for_device(int dev)
 }
 
 struct Layout {
-    size_t mirror_part = 0;
+    size_t mirror_part = 0, halo = 0;
     size_t systems, tiles, chain_id, chain_id2, P[3], C[3], Q[3], D[3], keys, hist, bsum, perm, base, delta, flux, chunks,
         omega, accept, status, partials, obs_out, staging, chain_class, chain_class2, conv, tgt, place_W, place_bsum,
         ptiles, total;   // base: counts, delta: density delta; ptiles: block tiles
@@ -145,6 +145,7 @@ struct soma_ctx {
     uint64_t *sweep_ctr() const { return reinterpret_cast<uint64_t *>(ws + L.status + 8); }
     // density mode 3: the copy blocks' sums of the count halves
     unsigned long long *mirror_part() const { return reinterpret_cast<unsigned long long *>(ws + L.mirror_part); }
+    uint2 *halo() const { return reinterpret_cast<uint2 *>(ws + L.halo); }
     double *partials() const { return reinterpret_cast<double *>(ws + L.partials); }
     double *obs_out() const { return reinterpret_cast<double *>(ws + L.obs_out); }
     void *staging() const { return ws + L.staging; }
@@ -376,6 +377,8 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     L.accept = take(sizeof(uint64_t) * soma::kAcceptSlots * soma::kAcceptStride * n_sys);
     L.status = take(64);
     L.mirror_part = take(sizeof(unsigned long long) * soma::kMirrorBlocks);
+    // stream tiles: two halo buffers of the end-lane pairs of every tile
+    L.halo = take(sizeof(uint2) * 2 * soma::kHaloSlots * 2 * (size_t)L.n_ptiles_cap);
     L.partials = take(sizeof(double) * 12 * max_blocks);
     L.obs_out = take(sizeof(double) * 8);
     L.staging = take(sizeof(float) * 2 * max_cells);
@@ -553,7 +556,32 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
     a.chain_class = c->chain_class();
     a.tgt = c->tgt();
     a.conv = c->conv();
+    a.halo = c->halo();
+    a.halo_cap = c->L.n_ptiles_cap;
     return a;
+}
+
+// Stream tiles: copy the end-lane pairs of every tile into halo buffer
+// (sweep mod 2), which the overlap lanes of the next sweep read.  Needed
+// before a batch of stream-tile sweeps and after anything else moved beads
+// or chains (other tilings, a reorder, set_positions, autotune's restore);
+// it runs before every batch and after every reorder.
+int refresh_halo(soma_ctx *c)
+{
+    if (c->packed != 2) return SOMA_OK;
+    soma::HaloArgs h{};
+    h.systems = c->d_sys();
+    h.ptiles = c->d_ptiles();
+    h.n_ptiles = c->n_ptiles;
+    for (int d = 0; d < 3; ++d) {
+        (&h.P0)[d] = c->P(d);
+        (&h.C0)[d] = c->C(d);
+    }
+    h.halo = c->halo();
+    h.halo_cap = c->L.n_ptiles_cap;
+    h.buf = (int)(c->sweep & 1);
+    HIPCHK(c, soma::launch_stream_halo(c->repr, h, c->stream));
+    return SOMA_OK;
 }
 
 // Bring the count buffers to the canonical layout (counts in base[0], every
@@ -929,13 +957,14 @@ int run_sweeps(soma_ctx *c, int32_t n, hipEvent_t *ev)
     int rc = SOMA_OK;
     if (n > 0 && (rc = sweep_layout(c)) != SOMA_OK) return rc;
     if (n > 0 && (rc = upload_block_tiles(c)) != SOMA_OK) return rc;
+    if (n > 0 && (rc = refresh_halo(c)) != SOMA_OK) return rc;
     const uint64_t R = (uint64_t)c->opt.reorder_every;
     int32_t left = n;
     while (left > 0) {
         // reorders happen at sweep counts that are multiples of R, however
         // the sweeps are split over calls
         if (R > 0 && c->sweep % R == 0 && c->last_reorder != c->sweep)
-            if ((rc = reorder_chains(c)) != SOMA_OK) return rc;
+            if ((rc = reorder_chains(c)) != SOMA_OK || (rc = refresh_halo(c)) != SOMA_OK) return rc;
         int32_t seg = left;
         if (R > 0) seg = (int32_t)std::min<uint64_t>((uint64_t)left, R - c->sweep % R);
         if (seg > kGraphChunk) seg = kGraphChunk;
@@ -1647,6 +1676,7 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
         drop_graphs(c);
         if ((rc = sweep_layout(c)) != SOMA_OK) return rc;
         if ((rc = upload_block_tiles(c)) != SOMA_OK) return rc;
+        if ((rc = refresh_halo(c)) != SOMA_OK) return rc;
         if ((rc = batch()) != SOMA_OK) return rc;
         HIPCHK(c, hipEventRecord(e0, c->stream));
         if ((rc = batch()) != SOMA_OK) return rc;
@@ -1664,7 +1694,15 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
     // wave tiles: one per wave, or resident grids of 8 or 32 waves per CU;
     // block tiles (-1 here): one per block; stream tiles (-2): one per wave
     static const int kWpb[] = {1, 2, 4, 8, 16}, kWpcu[] = {0, 8, 32, -1, -2}, kXcd[] = {1, 0}, kDm[] = {0, 1, 2, 3};
+    constexpr size_t kTuneFinalists = 4;
     const bool stream_ok = !c->any_smc && !any_coupling(c);
+    struct Cand {
+        double us;
+        int wpb, cu, xcd, dm, pk;
+    };
+    std::vector<Cand> cand;
+    cand.push_back({best.us_per_sweep, best.waves_per_block, best.waves_per_cu, best.xcd_remap, best.density_mode,
+                    best.packed_tiles});
     for (int dm : kDm)
         for (int wpb : kWpb)
             for (int wpcu : kWpcu)
@@ -1677,15 +1715,33 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
                     double us = 0.0;
                     rc = time_shape(wpb, cu, xcd, dm, pk, us);
                     ++best.n_candidates;
-                    if (rc == SOMA_OK && us < best.us_per_sweep) {
-                        best.us_per_sweep = us;
-                        best.waves_per_block = wpb;
-                        best.waves_per_cu = cu;
-                        best.xcd_remap = xcd;
-                        best.density_mode = dm;
-                        best.packed_tiles = pk;
-                    }
+                    if (rc == SOMA_OK) cand.push_back({us, wpb, cu, xcd, dm, pk});
                 }
+    // One timed batch per shape is noisy at the percent level, about the gap
+    // between the best shapes: the fastest few are timed twice more and
+    // ranked by the median of their three times.
+    if (rc == SOMA_OK) {
+        std::sort(cand.begin(), cand.end(), [](const Cand &x, const Cand &y) { return x.us < y.us; });
+        const size_t top = std::min<size_t>(cand.size(), kTuneFinalists);
+        for (size_t k = 0; k < top && rc == SOMA_OK; ++k) {
+            Cand &q = cand[k];
+            double t[3] = {q.us, 0.0, 0.0};
+            for (int r = 1; r < 3 && rc == SOMA_OK; ++r) rc = time_shape(q.wpb, q.cu, q.xcd, q.dm, q.pk, t[r]);
+            std::sort(t, t + 3);
+            q.us = t[1];
+        }
+        if (rc == SOMA_OK) {
+            const Cand *b = &cand[0];
+            for (size_t k = 1; k < top; ++k)
+                if (cand[k].us < b->us) b = &cand[k];
+            best.us_per_sweep = b->us;
+            best.waves_per_block = b->wpb;
+            best.waves_per_cu = b->cu;
+            best.xcd_remap = b->xcd;
+            best.density_mode = b->dm;
+            best.packed_tiles = b->pk;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SOMA_OK) return rc;

@@ -991,8 +991,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
 // bead reads lane 0's odd bead (unmoved in the even pass), and lane 62's odd
 // bead reads lane 63's even bead after lane 63 has made that bead's even move
 // with the same draw, stored state, frozen counts and arithmetic as the wave
-// that owns it, so the same decision.  A stream tile names its system (low
-// 24 bits), the pair index of its first owned lane within that lane's chain
+// that owns it, so the same decision.  The owners of the two overlap lanes
+// rewrite them during the same sweep, so the overlap lanes read them from
+// the halo copy taken before the sweep (halo_index): tile w - 1's last and
+// tile w + 1's first owned lane.  A stream tile names its system (low 24
+// bits), the pair index of its first owned lane within that lane's chain
 // (high 8 bits) and that chain.
 __device__ __forceinline__ uint32_t stile_sys(const Tile &T) { return T.sys & 0xFFFFFFu; }
 
@@ -1002,9 +1005,8 @@ struct StreamLane {
     bool own;       // and belongs to this wave: stores and counts
 };
 
-__device__ __forceinline__ StreamLane stream_lane(const Tile &T, const DevSys &S)
+__device__ __forceinline__ StreamLane stream_lane(const Tile &T, const DevSys &S, int lane)
 {
-    const int lane = (int)(threadIdx.x & 63);
     const int P = S.P;
     // stream lane 62 w - 1 + lane, as (chain0 - 1 + gr, q - gr P) with q >= 0
     const int q = (int)(T.sys >> 24) + lane - 1 + P;            // < 2 P + 63
@@ -1017,18 +1019,62 @@ __device__ __forceinline__ StreamLane stream_lane(const Tile &T, const DevSys &S
     return L;
 }
 
+// One bead pair in the halo: component k of both beads in one 8-byte word,
+// the components of one side contiguous (16-byte accesses).
+__device__ __forceinline__ void halo_put(uint2 *h, int buf, int64_t tile, int side, int64_t cap, const BeadF32 &a,
+                                         const BeadF32 &b)
+{
+    uint2 *e = h + halo_index(buf, 0, tile, side, cap);
+    *reinterpret_cast<uint4 *>(e) = make_uint4(__float_as_uint(a.x), __float_as_uint(b.x), __float_as_uint(a.y),
+                                               __float_as_uint(b.y));
+    e[2] = make_uint2(__float_as_uint(a.z), __float_as_uint(b.z));
+}
+__device__ __forceinline__ void halo_put(uint2 *h, int buf, int64_t tile, int side, int64_t cap, const BeadCell &a,
+                                         const BeadCell &b)
+{
+    uint4 *e = reinterpret_cast<uint4 *>(h + halo_index(buf, 0, tile, side, cap));
+    e[0] = make_uint4(__float_as_uint(a.ox), __float_as_uint(b.ox), __float_as_uint(a.oy), __float_as_uint(b.oy));
+    e[1] = make_uint4(__float_as_uint(a.oz), __float_as_uint(b.oz), (uint32_t)a.cx, (uint32_t)b.cx);
+    e[2] = make_uint4((uint32_t)a.cy, (uint32_t)b.cy, (uint32_t)a.cz, (uint32_t)b.cz);
+}
+__device__ __forceinline__ void halo_get(const uint2 *h, int buf, int64_t tile, int side, int64_t cap, BeadF32 &a,
+                                         BeadF32 &b)
+{
+    const uint2 *e = h + halo_index(buf, 0, tile, side, cap);
+    const uint4 xy = *reinterpret_cast<const uint4 *>(e);
+    const uint2 z = e[2];
+    a = BeadF32{__uint_as_float(xy.x), __uint_as_float(xy.z), __uint_as_float(z.x)};
+    b = BeadF32{__uint_as_float(xy.y), __uint_as_float(xy.w), __uint_as_float(z.y)};
+}
+__device__ __forceinline__ void halo_get(const uint2 *h, int buf, int64_t tile, int side, int64_t cap, BeadCell &a,
+                                         BeadCell &b)
+{
+    const uint4 *e = reinterpret_cast<const uint4 *>(h + halo_index(buf, 0, tile, side, cap));
+    const uint4 u = e[0], v = e[1], w = e[2];
+    a = BeadCell{(int)v.z, (int)w.x, (int)w.z, __uint_as_float(u.x), __uint_as_float(u.z), __uint_as_float(v.x)};
+    b = BeadCell{(int)v.w, (int)w.y, (int)w.w, __uint_as_float(u.y), __uint_as_float(u.w), __uint_as_float(v.y)};
+}
+
+// Owned lanes load their pairs from the position arrays; the overlap lanes
+// (valid only next to a tile of the same system: lane 0 when the tile does
+// not start its system's stream, lane 63 when the stream goes on) load them
+// from halo buffer s mod 2.
 template <class Bead>
-__device__ __forceinline__ void stream_load(const SweepArgs &a, int tile, Bead &b0, Bead &b1, uint32_t &clog)
+__device__ __forceinline__ void stream_load(const SweepArgs &a, int tile, uint64_t s, Bead &b0, Bead &b1,
+                                            uint32_t &clog)
 {
     const Tile T = a.ptiles[tile];
     const DevSys &S = a.systems[stile_sys(T)];
-    const StreamLane L = stream_lane(T, S);
+    const int lane = (int)(threadIdx.x & 63);
+    const StreamLane L = stream_lane(T, S, lane);
     clog = a.chain_id[S.chain_off + (L.valid ? L.chain : (int)T.chain0)];
     b0 = Bead{};
     b1 = Bead{};
-    if (L.valid)
+    if (L.own)
         load_pair(PosArrays{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2}, S.slot_off + (int64_t)L.chain * (2 * S.P) + 2 * L.p,
                   b0, b1);
+    else if (L.valid)
+        halo_get(a.halo, (int)(s & 1), lane == 0 ? tile - 1 : tile + 1, lane == 0 ? 1 : 0, a.halo_cap, b0, b1);
 }
 
 template <int R, int CW, int DM, class Bead>
@@ -1044,7 +1090,7 @@ __device__ __forceinline__ void sweep_tile_stream(const SweepArgs &a, int wave, 
     const bool frozen = S.frozen != 0;
     const int64_t cell_off = S.cell_off;
     const int N = S.N, P = S.P;
-    const StreamLane L = stream_lane(T, S);
+    const StreamLane L = stream_lane(T, S, (int)(threadIdx.x & 63));
     const bool valid = L.valid, own = L.own;
     const int p = L.p;
     const int i0 = 2 * p, i1 = 2 * p + 1;
@@ -1116,8 +1162,32 @@ __device__ __forceinline__ void sweep_tile_stream(const SweepArgs &a, int wave, 
     }
     const bool own1 = own && has1;
     if (own) store_moved(A, slot, b0, b1, ob0, ob1, acc0 || acc1);
+    // the end lanes' pairs for the overlap lanes of the next sweep
+    const int lane = (int)(threadIdx.x & 63);
+    if (own && (lane == 1 || lane == kStreamLanes))
+        halo_put(a.halo, (int)((s + 1) & 1), wave, lane == 1 ? 0 : 1, a.halo_cap, b0, b1);
     tile_finish<CW, DM>(a, wave, sys, cell_off, v, dcur, agg_keys, agg_vals, own && acc0 && nc0 != old0, c0, s0, t0,
                         t0, own1 && acc1 && nc1 != old1, c1, s1, t1, t1, own && acc0, own1 && acc1, own && bad);
+}
+
+// Fill halo buffer a.buf from the position arrays: one thread per stream
+// tile and end lane (side 0: lane 1, side 1: lane 62), for the lanes that
+// belong to their system.
+template <class Bead>
+__global__ __launch_bounds__(256) void k_stream_halo(HaloArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * (int64_t)a.n_ptiles) return;
+    const int64_t tile = i >> 1;
+    const int side = (int)(i & 1);
+    const Tile T = a.ptiles[tile];
+    const DevSys &S = a.systems[stile_sys(T)];
+    const StreamLane L = stream_lane(T, S, side == 0 ? 1 : kStreamLanes);
+    if (!L.own) return;
+    Bead b0, b1;
+    load_pair(PosArrays{a.P0, a.P1, a.P2, a.C0, a.C1, a.C2}, S.slot_off + (int64_t)L.chain * (2 * S.P) + 2 * L.p,
+              b0, b1);
+    halo_put(a.halo, a.buf, tile, side, a.halo_cap, b0, b1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1398,7 +1468,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
             if (wave < a.n_ptiles) {
                 Bead b0, b1;
                 uint32_t clog;
-                stream_load(a, wave, b0, b1, clog);
+                stream_load(a, wave, s, b0, b1, clog);
                 agg_clear<SLOTS>(agg_keys, agg_vals);
                 sweep_tile_stream<R, CW, DM>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog);
             }
@@ -2368,6 +2438,17 @@ hipError_t launch_mirror(int cw, const MirrorArgs &a, hipStream_t st)
     } else {
         hipLaunchKernelGGL((k_mirror<COUNT_U32>), dim3((unsigned)blocks), dim3(256), 0, st, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_halo(int repr, const HaloArgs &a, hipStream_t st)
+{
+    if (a.n_ptiles <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((2 * (int64_t)a.n_ptiles + 255) / 256);
+    if (repr == REPR_F32)
+        hipLaunchKernelGGL((k_stream_halo<BeadF32>), dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_stream_halo<BeadCell>), dim3(blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -45,6 +45,35 @@ struct SweepArgs {
     uint8_t *chain_class;          // per logical chain: 0 = pattern a, 1 = pattern b
     const float2 *tgt;             // umbrella target (phi_A, phi_B) per cell
     unsigned long long *conv;      // [n_sys][2]: chains converted to class a, to class b
+    uint2 *halo;                   // stream tiles: boundary bead pairs, see halo_index
+    int64_t halo_cap;              // stream tile entries per halo array
+};
+
+// Stream tiles read the bead pairs of their two overlap lanes, which other
+// waves own and rewrite during the same sweep, from a copy taken before the
+// sweep: halo buffer (s mod 2) holds, for every stream tile and both of its
+// end lanes (side 0: first owned lane, side 1: last owned lane), the pair as
+// it stands when sweep s starts, one 8-byte pair per position array
+// (component 0..2: coordinates or offsets, 3..5: cells).  A tile's entry is
+// one 128-byte line (two sides of eight pair slots), so a wave reads one
+// line of each neighbour and writes one line.  Sweep s writes buffer
+// (s + 1) mod 2 as its owners finish; the host refills buffer (s mod 2)
+// before a batch of sweeps and after a chain reorder.
+constexpr int kHaloComps = 6;
+constexpr int kHaloSlots = 8;      // pair slots per side (kHaloComps used)
+__host__ __device__ inline int64_t halo_index(int buf, int comp, int64_t tile, int side, int64_t cap)
+{
+    return (((int64_t)buf * cap + tile) * 2 + side) * kHaloSlots + comp;
+}
+struct HaloArgs {
+    const DevSys *systems;
+    const Tile *ptiles;
+    int n_ptiles;
+    float *P0, *P1, *P2;           // read only
+    int *C0, *C1, *C2;
+    uint2 *halo;
+    int64_t halo_cap;
+    int buf;
 };
 
 struct DensityArgs {
@@ -136,6 +165,7 @@ struct ObsArgs {
 };
 
 hipError_t launch_sweep(int repr, int cw, const SweepArgs &a, hipStream_t st);
+hipError_t launch_stream_halo(int repr, const HaloArgs &a, hipStream_t st);
 hipError_t launch_density(int repr, int cw, const DensityArgs &a, hipStream_t st);
 hipError_t launch_fields(int cw, const FieldArgs &a, hipStream_t st);
 hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off, int64_t n_cells,

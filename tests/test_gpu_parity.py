@@ -200,6 +200,37 @@ def test_stream_tile_parity(r, cw, dm):
     h.close()
 
 
+@pytest.mark.parametrize("name,n_sys,dm", [("batched_mixed", 24, 3), ("batched_uneven", 64, 1)])
+def test_stream_tiles_match_wave_tiles_at_scale(name, n_sys, dm):
+    """Stream tiles on a batch of millions of beads, where the waves of one
+    sweep run far apart in time: the overlap lanes read the pairs of their
+    neighbouring tiles from the copy taken before the sweep, never from
+    pairs the owning wave has already rewritten, so 30 sweeps (two calls,
+    a chain reorder every 10 sweeps) leave every system's state, density and
+    acceptance count bit-identical to wave tiles, on repeated runs too."""
+    systems = W.workload(name)[:n_sys]
+    opts = W.WORKLOAD_OPTIONS[name]
+    r, cw = opts["pos_repr"], opts["count_width"]
+    print(f"[stream at scale] {name}: {len(systems)} systems, {sum(s.n_beads for s in systems)} beads, dm {dm}",
+          flush=True)
+    h = Soma(systems, seed=SEED, pos_repr=r, count_width=cw, reorder_every=10)
+    h.sweep(30)
+    for run in range(2):
+        g = Soma(systems, seed=SEED, pos_repr=r, count_width=cw, reorder_every=10, density_mode=dm, packed_tiles=2,
+                 waves_per_block=4)
+        assert g.info()["packed_tiles"] == 2
+        g.sweep(12)
+        g.sweep(18)
+        bad = [k for k in range(len(systems)) if not _same_state(g.state(k), h.state(k))]
+        print(f"[stream at scale] run {run}: {len(bad)} of {len(systems)} systems differ from wave tiles", flush=True)
+        assert not bad, bad[:8]
+        for k in range(len(systems)):
+            assert (g.density(k) == h.density(k)).all(), k
+            assert g.observables(k)["n_accepted"] == h.observables(k)["n_accepted"], k
+        g.close()
+    h.close()
+
+
 def test_stream_tiles_fall_back_with_smart_moves():
     """Stream tiles are asked for but the context moves with smart moves: the
     shape reports wave tiles and the sweep matches a wave-tile context."""

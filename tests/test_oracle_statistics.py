@@ -5,11 +5,12 @@ Ideal chains (chiN = kappaN = 0, so every field is zero):
     k = 3(N-1)/Re^2: <Re^2> = Re^2, <Rg^2> = Re^2 (N+1)/(6N),
     <E_bond>/chain = 3(N-1)/2, bond components N(0, Re^2/(3(N-1)));
   * sweeps keep that distribution;
-  * the acceptance ratio has a closed form (derived in the design doc): for a trial
-    displacement d, dE is Gaussian with mean mu and variance 2 mu, mu = k|d|^2
-    for an interior bead and k|d|^2/2 for an end bead, so
-    P(accept | d) = 2 Phi(-sqrt(mu/2)); averaging over the uniform cube is done
-    here by Gauss-Legendre quadrature, independently of the oracle.
+  * the acceptance ratio has a closed form: for a trial displacement d, dE is
+    Gaussian with mean mu and variance 2 mu, mu = k|d|^2 for an interior bead
+    and k|d|^2/2 for an end bead; exp(-dE) times that density is the same
+    Gaussian centred at -mu, so P(accept | d) = E[min(1, exp(-dE))] =
+    2 Phi(-sqrt(mu/2)); averaging over the uniform cube is done here by
+    Gauss-Legendre quadrature, independently of the oracle.
 Two-bead chains (N = 2):
   * the bond length follows the Maxwell law with k = 3;
   * with a frozen random field on a 4^3 grid the joint cell occupancy equals
