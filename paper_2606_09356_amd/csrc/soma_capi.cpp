@@ -95,7 +95,8 @@ struct soma_ctx {
     int waves_per_cu = 0, n_cus = 0;
     int packed = 0;                    // sweep launched over block tiles
     int n_ptiles = 0;
-    std::vector<Tile> ptiles_host;     // the block tiles of the current waves_per_block
+    std::vector<Tile> ptiles_host;     // the block or stream tiles on the device
+    int ptiles_packed = 0, ptiles_wpb = 0;   // the tiling and waves per block they were built for
     int device = 0;                    // the GPU the context was created on
     double *scratch_dev = nullptr;     // that GPU's static scratch (soma_observables_noalloc)
     // density_mode 1 keeps the counts in rotation (base[(s+1)&1] + delta[(s+2)%3]
@@ -449,6 +450,12 @@ void set_shape(soma_ctx *c, int waves_per_block, int waves_per_cu, int xcd_remap
 int upload_block_tiles(soma_ctx *c)
 {
     if (!c->packed) return SOMA_OK;
+    // the table depends on the systems (fixed) and the tiling only: this
+    // runs before every batch, and rebuilding a million-entry table costs
+    // milliseconds of host time in front of the launch
+    if (c->n_ptiles > 0 && c->ptiles_packed == c->packed &&
+        (c->packed == 2 || c->ptiles_wpb == c->waves_per_block))
+        return SOMA_OK;
     std::vector<Tile> t;
     if (c->packed == 2) {
         if (c->sys.size() >= (size_t(1) << 24)) return fail(c, SOMA_EINVAL, "stream tiles hold at most 2^24 systems");
@@ -465,13 +472,11 @@ int upload_block_tiles(soma_ctx *c)
         }
     }
     if ((int64_t)t.size() > c->L.n_ptiles_cap) return fail(c, SOMA_EDEVICE, "block tile table overflow");
-    if (t.size() == c->ptiles_host.size() && c->n_ptiles == (int)t.size() &&
-        std::equal(t.begin(), t.end(), c->ptiles_host.begin(),
-                   [](const Tile &x, const Tile &y) { return x.sys == y.sys && x.chain0 == y.chain0; }))
-        return SOMA_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));     // the previous table may still be in flight
     c->ptiles_host = std::move(t);
     c->n_ptiles = (int)c->ptiles_host.size();
+    c->ptiles_packed = c->packed;
+    c->ptiles_wpb = c->waves_per_block;
     HIPCHK(c, hipMemcpyAsync(c->d_ptiles(), c->ptiles_host.data(), sizeof(Tile) * c->ptiles_host.size(),
                              hipMemcpyHostToDevice, c->stream));
     return SOMA_OK;
