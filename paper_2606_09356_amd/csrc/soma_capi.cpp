@@ -111,6 +111,10 @@ struct soma_ctx {
     // mode-3 sweeps begin, kept by them, dropped by anything else that
     // writes the counts)
     bool mirror = false;
+    // stream tiles: the sweep whose start state halo buffer (sweep mod 2)
+    // holds; anything that writes positions other than a stream-tile sweep
+    // marks it stale (all ones)
+    uint64_t halo_sweep = ~uint64_t(0);
     int any_smc = 0;       // some system moves with bond-force-biased moves
     int any_zones = 0;     // some system has conversion zones (density mode 2 excluded)
     uint64_t sweep = 0;
@@ -568,12 +572,12 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
 
 // Stream tiles: copy the end-lane pairs of every tile into halo buffer
 // (sweep mod 2), which the overlap lanes of the next sweep read.  Needed
-// before a batch of stream-tile sweeps and after anything else moved beads
-// or chains (other tilings, a reorder, set_positions, autotune's restore);
-// it runs before every batch and after every reorder.
+// before a batch of stream-tile sweeps unless the last stream-tile sweep
+// left it (halo_sweep): after other tilings, a reorder, the init,
+// set_positions, set_state, placement, set_sweep or autotune's restore.
 int refresh_halo(soma_ctx *c)
 {
-    if (c->packed != 2) return SOMA_OK;
+    if (c->packed != 2 || c->halo_sweep == c->sweep) return SOMA_OK;
     soma::HaloArgs h{};
     h.systems = c->d_sys();
     h.ptiles = c->d_ptiles();
@@ -586,6 +590,7 @@ int refresh_halo(soma_ctx *c)
     h.halo_cap = c->L.n_ptiles_cap;
     h.buf = (int)(c->sweep & 1);
     HIPCHK(c, soma::launch_stream_halo(c->repr, h, c->stream));
+    c->halo_sweep = c->sweep;
     return SOMA_OK;
 }
 
@@ -629,6 +634,10 @@ int sweep_layout(soma_ctx *c)
     if (c->density_mode == 3 && !c->mirror) {
         HIPCHK(c, hipMemcpyAsync(c->base(1), c->base(0), sizeof(uint32_t) * c->L.count_words,
                                  hipMemcpyDeviceToDevice, c->stream));
+        // the running half sums of the copy blocks start at zero (every
+        // batch's check clears them again)
+        HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->mirror_part()), 2 * soma::kMirrorBlocks, 0u,
+                                        c->stream));
         c->mirror = true;
     }
     if (c->density_mode != 3) c->mirror = false;
@@ -790,7 +799,21 @@ int reorder_chains(soma_ctx *c)
     HIPCHK(c, hipMemcpyAsync(c->chain_id(), r.chain_id2, sizeof(uint32_t) * (size_t)c->L.total_chains,
                              hipMemcpyDeviceToDevice, c->stream));
     c->last_reorder = c->sweep;
+    c->halo_sweep = ~uint64_t(0);
     return SOMA_OK;
+}
+
+soma::MirrorArgs mirror_args(const soma_ctx *c, uint32_t rel)
+{
+    soma::MirrorArgs m{};
+    m.base = c->base(0);
+    m.count_words = c->L.count_words;
+    m.sweep_ctr = c->sweep_ctr();
+    m.rel = rel;
+    m.part = c->mirror_part();
+    m.beads = (unsigned long long)c->L.total_beads;
+    m.status = c->status();
+    return m;
 }
 
 // Enqueue n sweeps on stream st.  With ev (3 events per sweep), sweep r
@@ -817,19 +840,10 @@ int record_sweeps(soma_ctx *c, int32_t n, hipStream_t st, hipEvent_t *ev = nullp
             f.status = c->status();
             HIPCHK(c, soma::launch_fold_faces(c->cw, f, c->L.n_chunks, st));
         }
-        if (c->density_mode == 3) {
-            soma::MirrorArgs m{};
-            m.base = c->base(0);
-            m.count_words = c->L.count_words;
-            m.sweep_ctr = c->sweep_ctr();
-            m.rel = (uint32_t)r;
-            m.part = c->mirror_part();
-            m.beads = (unsigned long long)c->L.total_beads;
-            m.status = c->status();
-            HIPCHK(c, soma::launch_mirror(c->cw, m, st));
-        }
+        if (c->density_mode == 3) HIPCHK(c, soma::launch_mirror(c->cw, mirror_args(c, (uint32_t)r), st));
         if (ev) HIPCHK(c, hipEventRecord(ev[3 * r + 2], st));
     }
+    if (c->density_mode == 3 && n > 0) HIPCHK(c, soma::launch_mirror_check(c->cw, mirror_args(c, 0), (uint32_t)n, st));
     HIPCHK(c, soma::launch_advance(c->sweep_ctr(), (uint32_t)n, st));
     return SOMA_OK;
 }
@@ -934,6 +948,7 @@ int download_slots(soma_ctx *c, const HostSys &h, std::vector<float> (&P)[3], st
 // Upload slots given in logical chain order to the current physical order.
 int upload_slots(soma_ctx *c, const HostSys &h, const std::vector<float> (&P)[3], const std::vector<int> (&Cv)[3])
 {
+    c->halo_sweep = ~uint64_t(0);
     const size_t stride = 2 * (size_t)h.dev.P, n = (size_t)h.d.n_chains * stride;
     std::vector<uint32_t> cid;
     int rc = fetch_chain_ids(c, h, cid);
@@ -984,6 +999,7 @@ int run_sweeps(soma_ctx *c, int32_t n, hipEvent_t *ev)
         c->sweep += (uint64_t)seg;
         c->swept += (uint64_t)seg;
         left -= seg;
+        if (c->packed == 2) c->halo_sweep = c->sweep;   // the sweeps wrote the next start state
     }
     if (n > 0 && c->density_mode == 2) {
         c->flux_dirty = true;
@@ -1484,6 +1500,7 @@ int soma_place_from_fields(soma_ctx *c, int32_t sys, const float *phi)
     pa.W = reinterpret_cast<unsigned long long *>(c->ws + c->L.place_W);
     pa.na[0] = na_k[0];
     pa.na[1] = na_k[1];
+    c->halo_sweep = ~uint64_t(0);
     HIPCHK(c, soma::launch_place(pa, reinterpret_cast<unsigned long long *>(c->ws + c->L.place_bsum), c->stream));
     h.has_target = true;
     if ((rc = rebuild_density(c, sys)) != SOMA_OK) return rc;
@@ -1547,6 +1564,7 @@ int soma_set_sweep(soma_ctx *c, uint64_t sweep)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->sweep_ctr(), &sweep, sizeof sweep, hipMemcpyHostToDevice));
     c->sweep = sweep;
+    c->halo_sweep = ~uint64_t(0);
     if ((rc = rebuild_density(c, -1)) != SOMA_OK) return rc;
     return sync_status(c);
 }
@@ -1646,6 +1664,7 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
     auto restore = [&]() -> int {
         if ((rc = canonicalize(c)) != SOMA_OK) return rc;
         c->sweep = host_sweep;
+        c->halo_sweep = ~uint64_t(0);
         for (int d = 0; d < 3; ++d) {
             HIPCHK(c, hipMemcpyAsync(c->P(d), c->Q(d), pos_bytes, hipMemcpyDeviceToDevice, c->stream));
             if (c->repr == soma::REPR_CELL)

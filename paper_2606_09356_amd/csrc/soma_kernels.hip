@@ -1619,11 +1619,13 @@ __global__ __launch_bounds__(256) void k_fold(const uint32_t *in, uint32_t *delt
 // +-1 or +-2^16 on the word, and a true count never goes below zero during
 // the sweep (a bead leaves only a cell it was counted in at the start), so
 // the word is exact unless a count passed 65535: then its carry moves into
-// the other half or out of the word, which lowers the sum of all halves.  So
-// each block also writes the sum of the halves it copied, and k_mirror_check
-// compares the total with the number of beads.  (Plain stores and a second
-// kernel instead of a last-block reduction: a device-scope fence per block
-// would write back the L2 each time.)
+// the other half or out of the word, which lowers the sum of all halves, and
+// the error stays in the counts.  So each block adds the sum of the halves
+// it copied to its running entry of a.part (the same block index copies the
+// same words every sweep), and k_mirror_check, once after the last sweep of
+// a batch, compares the total with (sweeps) x (beads).  (Plain stores and a
+// second kernel instead of a last-block reduction: a device-scope fence per
+// block would write back the L2 each time.)
 template <int CW>
 __global__ __launch_bounds__(256) void k_mirror(MirrorArgs a)
 {
@@ -1655,24 +1657,28 @@ __global__ __launch_bounds__(256) void k_mirror(MirrorArgs a)
         for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o);
         if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
         __syncthreads();
-        if (threadIdx.x == 0) a.part[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+        if (threadIdx.x == 0) a.part[blockIdx.x] += part[0] + part[1] + part[2] + part[3];
     }
 }
 
-// Sum of the copy blocks' half sums against the number of beads (one block).
-__global__ __launch_bounds__(1024) void k_mirror_check(const unsigned long long *part, int n_part,
-                                                       unsigned long long beads, uint32_t *status)
+// Running half sums of the copy blocks against (sweeps) x (beads); clears
+// them for the next batch (one block; each thread clears what it read).
+__global__ __launch_bounds__(1024) void k_mirror_check(unsigned long long *part, int n_part,
+                                                       unsigned long long expected, uint32_t *status)
 {
     __shared__ unsigned long long red[16];
     unsigned long long sum = 0;
-    for (int i = threadIdx.x; i < n_part; i += blockDim.x) sum += part[i];
+    for (int i = threadIdx.x; i < n_part; i += blockDim.x) {
+        sum += part[i];
+        part[i] = 0ull;
+    }
     for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
-        if (t != beads) atomicOr(status, ST_COUNT_OVERFLOW);
+        if (t != expected) atomicOr(status, ST_COUNT_OVERFLOW);
     }
 }
 
@@ -2427,17 +2433,28 @@ hipError_t launch_fold_faces(int cw, const FoldFacesArgs &a, int n_chunks, hipSt
     return hipGetLastError();
 }
 
+static int64_t mirror_blocks(int64_t count_words)
+{
+    const int64_t blocks = (count_words / 4 + 256 * kMirrorUnroll - 1) / (256 * kMirrorUnroll);
+    return blocks > kMirrorBlocks ? kMirrorBlocks : blocks;
+}
+
 hipError_t launch_mirror(int cw, const MirrorArgs &a, hipStream_t st)
 {
     if (a.count_words <= 0) return hipSuccess;
-    int64_t blocks = (a.count_words / 4 + 256 * kMirrorUnroll - 1) / (256 * kMirrorUnroll);
-    if (blocks > kMirrorBlocks) blocks = kMirrorBlocks;
-    if (cw == COUNT_U16) {
+    const int64_t blocks = mirror_blocks(a.count_words);
+    if (cw == COUNT_U16)
         hipLaunchKernelGGL((k_mirror<COUNT_U16>), dim3((unsigned)blocks), dim3(256), 0, st, a);
-        hipLaunchKernelGGL(k_mirror_check, dim3(1), dim3(1024), 0, st, a.part, (int)blocks, a.beads, a.status);
-    } else {
+    else
         hipLaunchKernelGGL((k_mirror<COUNT_U32>), dim3((unsigned)blocks), dim3(256), 0, st, a);
-    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mirror_check(int cw, const MirrorArgs &a, uint32_t n_sweeps, hipStream_t st)
+{
+    if (a.count_words <= 0 || cw != COUNT_U16 || n_sweeps == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mirror_check, dim3(1), dim3(1024), 0, st, a.part, (int)mirror_blocks(a.count_words),
+                       a.beads * (unsigned long long)n_sweeps, a.status);
     return hipGetLastError();
 }
 

@@ -193,8 +193,10 @@ hipError_t launch_fold(int cw, const uint32_t *counts_in, uint32_t *delta, uint3
                        uint32_t *status, hipStream_t st);
 // Density mode 3: after sweep s, copy base[(s+1) mod 2] (the counts the
 // sweep's atomics produced) into base[s mod 2]; for packed 16-bit counts
-// also check that the halves sum to the number of beads (each copy block
-// writes its part to `part`, a second one-block kernel adds them up).
+// also check that the halves sum to the number of beads: each copy block
+// adds the sum of the halves it copied to its entry of `part`, and after
+// the last sweep of a batch a one-block kernel compares the total with
+// (sweeps of the batch) x (beads) and clears `part` for the next batch.
 constexpr int kMirrorBlocks = 32768;
 constexpr int kMirrorUnroll = 4;   // 16-byte words per thread per step
 struct MirrorArgs {
@@ -202,11 +204,13 @@ struct MirrorArgs {
     int64_t count_words;           // a multiple of 4
     const uint64_t *sweep_ctr;
     uint32_t rel;
-    unsigned long long *part;      // kMirrorBlocks partial sums of the count halves
+    unsigned long long *part;      // kMirrorBlocks running sums of the count halves (zero between batches)
     unsigned long long beads;      // beads of the context
     uint32_t *status;
 };
 hipError_t launch_mirror(int cw, const MirrorArgs &a, hipStream_t st);
+// After n_sweeps mirrors of a batch (packed 16-bit counts only).
+hipError_t launch_mirror_check(int cw, const MirrorArgs &a, uint32_t n_sweeps, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_advance(uint64_t *ctr, uint32_t n, hipStream_t st);
 hipError_t launch_init(const InitArgs &a, hipStream_t st);

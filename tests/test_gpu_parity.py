@@ -231,6 +231,37 @@ def test_stream_tiles_match_wave_tiles_at_scale(name, n_sys, dm):
     h.close()
 
 
+def test_stream_tiles_refresh_the_halo_after_new_positions():
+    """The halo copy is refilled when positions change outside a stream-tile
+    sweep (set_positions, set_state, set_sweep) and reused between calls
+    otherwise: a stream-tile context and a wave-tile context given the same
+    new positions mid-run stay bit-identical."""
+    systems = stream_systems()
+    g = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, density_mode=3, packed_tiles=2, waves_per_block=4)
+    h = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, density_mode=3)
+    assert g.info()["packed_tiles"] == 2
+    for x in (g, h):
+        x.sweep(3)
+    for k, s in enumerate(systems):
+        xyz = W.gaussian_walks(s, seed=99 + k)
+        g.set_positions(k, xyz)
+        h.set_positions(k, xyz)
+    for x in (g, h):
+        x.sweep(2)
+        x.sweep(2)
+    st = h.state(1)
+    g.set_state(1, *st)
+    h.set_state(1, *st)
+    for x in (g, h):
+        x.set_sweep(50)
+        x.sweep(3)
+    for k in range(len(systems)):
+        assert _same_state(g.state(k), h.state(k)), k
+        assert (g.density(k) == h.density(k)).all(), k
+    g.close()
+    h.close()
+
+
 def test_stream_tiles_fall_back_with_smart_moves():
     """Stream tiles are asked for but the context moves with smart moves: the
     shape reports wave tiles and the sweep matches a wave-tile context."""
