@@ -138,7 +138,8 @@ typedef struct {
                                      count buffers and adds its -1/+1 words straight into the
                                      other, then a copy kernel makes them equal again (half
                                      the upkeep traffic of mode 0; packed 16-bit overflow is
-                                     caught by an exact check of the total bead count) */
+                                     caught by an exact check of the total bead count after
+                                     each batch of sweeps) */
     int32_t reorder_every;     /* >0: spatially sort chains every this many sweeps; 0: never */
     int32_t waves_per_block;   /* 1..16 waves per workgroup; 0: library default */
     int32_t waves_per_cu;      /* >0: sweep grid of this many waves per compute unit, each wave
