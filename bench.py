@@ -20,8 +20,8 @@ Batched vs plain at matched Re^2 error:
     32^3 Re box, 128^3 grid, FP32 positions (its Re^2 representation error,
     1.5e-5 relative against FP64 positions, is larger than the cell form's
     1.1e-10, so the batched form's accuracy is at least matched).
-Extra legs (on by default, --no-extra to skip): the 256-system single-chain
-workload at 1000 sweeps, the 16.8M-bead mixed-precision system, the 64
+Extra legs (on by default, --no-extra to skip): the small plain system (256
+chains, 8192 beads) at 1000 sweeps, the 16.8M-bead mixed-precision system, the 64
 uneven systems against the same systems run one after another, and the
 bond-force-biased (smart) move workload.
 
@@ -31,7 +31,8 @@ read and field write: 36 B for FP32 positions with packed uint16 counts, 60 B
 for cell + offset with uint16, 64 B for cell + offset with uint32) times the
 beads of one sweep, divided by the sweep's duration (HIP events on the
 context stream; a sweep is the sweep kernel plus its count upkeep: the fold
-kernel in density modes 0 and 2, the copy and its check in mode 3).  The
+kernel in density modes 0 and 2, the copy in mode 3, whose count check runs
+once per batch of sweeps).  The
 per-kernel split is measured with HIP events around each launch
 (soma_time_kernels) after the timed runs; the HBM traffic of a sweep comes
 from the committed rocprofv3 counters (profiles/sweep_<workload>_*), reported
@@ -178,7 +179,7 @@ def roofline_of(res, prof=None):
         if prof else "no profile of the current kernel source and density mode",
          "bytes_per_move": bpm, "bytes_per_sweep": per_sweep,
          "launch": "one sweep: the sweep kernel, then the count upkeep (fold in density modes 0 and 2, "
-                  "copy and check in mode 3)",
+                  "copy in mode 3, its count check once per batch of sweeps)",
          "sweep_us_hip_events": res["sweep_us"],
          "library_model_bytes_per_sweep": res["info"]["bytes_per_sweep"]}
     if "kernel_us" in res:
