@@ -52,7 +52,7 @@ double *scratch_for_device(int dev)
 }
 
 struct Layout {
-    size_t mirror_part = 0, halo = 0;
+    size_t mirror_part = 0, halo = 0, acc_tile = 0;
     size_t systems, tiles, chain_id, chain_id2, P[3], C[3], Q[3], D[3], keys, hist, bsum, perm, base, delta, flux, chunks,
         omega, accept, status, partials, obs_out, staging, chain_class, chain_class2, conv, tgt, place_W, place_bsum,
         ptiles, total;   // base: counts, delta: density delta; ptiles: block tiles
@@ -115,6 +115,9 @@ struct soma_ctx {
     // holds; anything that writes positions other than a stream-tile sweep
     // marks it stale (all ones)
     uint64_t halo_sweep = ~uint64_t(0);
+    // which tile table indexes the counts pending in acc_tile: -1 none (all
+    // zero), 0 wave tiles, 2 stream tiles
+    int acc_kind = -1;
     int any_smc = 0;       // some system moves with bond-force-biased moves
     int any_zones = 0;     // some system has conversion zones (density mode 2 excluded)
     uint64_t sweep = 0;
@@ -151,6 +154,7 @@ struct soma_ctx {
     // density mode 3: the copy blocks' sums of the count halves
     unsigned long long *mirror_part() const { return reinterpret_cast<unsigned long long *>(ws + L.mirror_part); }
     uint2 *halo() const { return reinterpret_cast<uint2 *>(ws + L.halo); }
+    unsigned long long *acc_tile() const { return reinterpret_cast<unsigned long long *>(ws + L.acc_tile); }
     double *partials() const { return reinterpret_cast<double *>(ws + L.partials); }
     double *obs_out() const { return reinterpret_cast<double *>(ws + L.obs_out); }
     void *staging() const { return ws + L.staging; }
@@ -384,6 +388,8 @@ Layout plan(const soma_system_desc *sys, int32_t n_sys, const soma_options *opt,
     L.mirror_part = take(sizeof(unsigned long long) * soma::kMirrorBlocks);
     // stream tiles: two halo buffers of the end-lane pairs of every tile
     L.halo = take(sizeof(uint2) * 2 * soma::kHaloSlots * 2 * (size_t)L.n_ptiles_cap);
+    // accepted moves per wave or stream tile (counts_per_tile)
+    L.acc_tile = take(sizeof(unsigned long long) * (size_t)std::max<int64_t>(tiles, L.n_ptiles_cap));
     L.partials = take(sizeof(double) * 12 * max_blocks);
     L.obs_out = take(sizeof(double) * 8);
     L.staging = take(sizeof(float) * 2 * max_cells);
@@ -567,7 +573,33 @@ soma::SweepArgs sweep_args(const soma_ctx *c, uint32_t rel)
     a.conv = c->conv();
     a.halo = c->halo();
     a.halo_cap = c->L.n_ptiles_cap;
+    a.acc_tile = c->acc_tile();   // the launch keeps it only for kernels that count per tile
     return a;
+}
+
+// Add the per-tile acceptance counts to the per-system counters and clear
+// them (before the tile table they index changes, and before a read).
+int fold_acc(soma_ctx *c)
+{
+    if (c->acc_kind < 0) return SOMA_OK;
+    const bool stream = c->acc_kind == 2;
+    HIPCHK(c, soma::launch_acc_fold(stream ? c->d_ptiles() : c->d_tiles(), stream ? c->n_ptiles : c->L.n_tiles,
+                                    stream, c->acc_tile(), c->accept(), c->stream));
+    c->acc_kind = -1;
+    return SOMA_OK;
+}
+
+// Before sweeps in the current shape, which runs before any new block or
+// stream tile table is uploaded: fold counts kept under another table.
+int prepare_acc(soma_ctx *c)
+{
+    const int kind = soma::counts_per_tile(sweep_args(c, 0)) ? (c->packed == 2 ? 2 : 0) : -1;
+    if (c->acc_kind >= 0 && c->acc_kind != kind) {
+        int rc = fold_acc(c);
+        if (rc != SOMA_OK) return rc;
+    }
+    if (kind >= 0) c->acc_kind = kind;
+    return SOMA_OK;
 }
 
 // Stream tiles: copy the end-lane pairs of every tile into halo buffer
@@ -976,6 +1008,7 @@ int run_sweeps(soma_ctx *c, int32_t n, hipEvent_t *ev)
 {
     int rc = SOMA_OK;
     if (n > 0 && (rc = sweep_layout(c)) != SOMA_OK) return rc;
+    if (n > 0 && (rc = prepare_acc(c)) != SOMA_OK) return rc;
     if (n > 0 && (rc = upload_block_tiles(c)) != SOMA_OK) return rc;
     if (n > 0 && (rc = refresh_halo(c)) != SOMA_OK) return rc;
     const uint64_t R = (uint64_t)c->opt.reorder_every;
@@ -1013,7 +1046,9 @@ int run_sweeps(soma_ctx *c, int32_t n, hipEvent_t *ev)
 // the six sums in `result`; allocates nothing.
 int observables_into(soma_ctx *c, int32_t sys, soma_obs *out, double *partials, double *result)
 {
-    int rc = canonicalize(c);
+    int rc = fold_acc(c);
+    if (rc != SOMA_OK) return rc;
+    rc = canonicalize(c);
     if (rc != SOMA_OK) return rc;
     const HostSys &h = c->sys[sys];
     soma::ObsArgs a{};
@@ -1153,6 +1188,8 @@ int soma_create(const soma_system_desc *sys, int32_t n_sys, const soma_options *
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->omega()), 2 * c->L.total_cells, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->accept()),
                                              2 * (int64_t)soma::kAcceptSlots * soma::kAcceptStride * n_sys, 0u, c->stream));
+             HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->acc_tile()),
+                                             2 * std::max<int64_t>(c->L.n_tiles, c->L.n_ptiles_cap), 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(c->status(), 16, 0u, c->stream));
              HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->conv()), 4 * (int64_t)n_sys, 0u, c->stream));
              return (int)SOMA_OK;
@@ -1637,6 +1674,7 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
     uint64_t ctr = 0;
     const uint64_t host_sweep = c->sweep;
     if ((rc = canonicalize(c)) != SOMA_OK) return rc;
+    if ((rc = fold_acc(c)) != SOMA_OK) return rc;     // the counters saved below hold every acceptance
     // save what trial sweeps change: positions (to the reorder scratch),
     // acceptance counters, status and the device sweep counter
     for (int d = 0; d < 3; ++d) {
@@ -1699,6 +1737,7 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
         c->density_mode = dm;
         drop_graphs(c);
         if ((rc = sweep_layout(c)) != SOMA_OK) return rc;
+        if ((rc = prepare_acc(c)) != SOMA_OK) return rc;
         if ((rc = upload_block_tiles(c)) != SOMA_OK) return rc;
         if ((rc = refresh_halo(c)) != SOMA_OK) return rc;
         if ((rc = batch()) != SOMA_OK) return rc;
@@ -1776,6 +1815,9 @@ int soma_autotune(soma_ctx *c, int32_t trial_sweeps, soma_tune *out)
     // undo the trial sweeps
     if ((rc = restore()) != SOMA_OK) return rc;
     HIPCHK(c, hipMemcpyAsync(c->accept(), acc.data(), acc_words * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, soma::launch_fill_u32(reinterpret_cast<uint32_t *>(c->acc_tile()),
+                                    2 * std::max<int64_t>(c->L.n_tiles, c->L.n_ptiles_cap), 0u, c->stream));
+    c->acc_kind = -1;
     HIPCHK(c, hipMemcpyAsync(c->status(), status.data(), 16 * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->conv(), conv.data(), sizeof(unsigned long long) * conv.size(), hipMemcpyHostToDevice,
                              c->stream));

@@ -781,7 +781,7 @@ __device__ __forceinline__ void tile_finish(const SweepArgs &a, int wave, uint32
                                             const SysView &v, uint32_t *dcur, uint32_t *agg_keys,
                                             uint32_t *agg_vals, bool m0, const CellPos &o0, const CellPos &f0,
                                             int t0, int u0, bool m1, const CellPos &o1, const CellPos &f1, int t1,
-                                            int u1, bool acc0, bool acc1, bool bad)
+                                            int u1, bool acc0, bool acc1, bool bad, unsigned long long acc_prev)
 {
     constexpr int SLOTS = DM == 2 ? kAggSlotsFaces : kAggSlotsCells;
     const int lane = (int)(threadIdx.x & 63);
@@ -804,7 +804,9 @@ __device__ __forceinline__ void tile_finish(const SweepArgs &a, int wave, uint32
     const uint64_t nacc = __popcll(__ballot(acc0)) + __popcll(__ballot(acc1));
     const bool any_bad = __ballot(bad) != 0;
     if (lane == 0) {
-        if (nacc)
+        if (nacc && a.acc_tile)   // this wave owns tile `wave` for the sweep
+            a.acc_tile[wave] = acc_prev + nacc;
+        else if (nacc)
             atomicAdd(a.accept + ((int64_t)sys * kAcceptSlots + (wave % kAcceptSlots)) * kAcceptStride,
                       (unsigned long long)nacc);
         if (any_bad) atomicOr(a.status, ST_CELL_OVERFLOW);
@@ -858,7 +860,8 @@ __device__ __forceinline__ float umb_step(float coef, float2 tn, float2 to, int 
 template <int R, int CW, int DM, bool CPL, bool BT, class Bead>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                            const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
-                                           uint32_t *agg_vals, Bead b0, Bead b1, uint32_t clog)
+                                           uint32_t *agg_vals, Bead b0, Bead b1, uint32_t clog,
+                                           unsigned long long acc_prev = 0ull)
 {
     const Tile T = tile_table<BT>(a)[wave];
     const DevSys &S = a.systems[T.sys];
@@ -976,7 +979,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int wave, uint64_
     }
     tile_finish<CW, DM>(a, BT ? wave * 16 + (int)(threadIdx.x >> 6) : wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals,
                         active && ((acc0 && nc0 != old0) || u0 != t0), c0, f0, t0, u0,
-                        has1 && ((acc1 && nc1 != old1) || u1 != t1), c1, f1, t1, u1, acc0, acc1, active && bad);
+                        has1 && ((acc1 && nc1 != old1) || u1 != t1), c1, f1, t1, u1, acc0, acc1, active && bad, acc_prev);
 }
 
 // ---------------------------------------------------------------------------
@@ -1080,7 +1083,8 @@ __device__ __forceinline__ void stream_load(const SweepArgs &a, int tile, uint64
 template <int R, int CW, int DM, class Bead>
 __device__ __forceinline__ void sweep_tile_stream(const SweepArgs &a, int wave, uint64_t s, const uint32_t *cin,
                                                   const uint32_t *dprev, uint32_t *dcur, uint32_t *agg_keys,
-                                                  uint32_t *agg_vals, Bead b0, Bead b1, uint32_t clog)
+                                                  uint32_t *agg_vals, Bead b0, Bead b1, uint32_t clog,
+                                                  unsigned long long acc_prev)
 {
     const Tile T = a.ptiles[wave];
     const uint32_t sys = stile_sys(T);
@@ -1167,7 +1171,7 @@ __device__ __forceinline__ void sweep_tile_stream(const SweepArgs &a, int wave, 
     if (own && (lane == 1 || lane == kStreamLanes))
         halo_put(a.halo, (int)((s + 1) & 1), wave, lane == 1 ? 0 : 1, a.halo_cap, b0, b1);
     tile_finish<CW, DM>(a, wave, sys, cell_off, v, dcur, agg_keys, agg_vals, own && acc0 && nc0 != old0, c0, s0, t0,
-                        t0, own1 && acc1 && nc1 != old1, c1, s1, t1, t1, own && acc0, own1 && acc1, own && bad);
+                        t0, own1 && acc1 && nc1 != old1, c1, s1, t1, t1, own && acc0, own1 && acc1, own && bad, acc_prev);
 }
 
 // Fill halo buffer a.buf from the position arrays: one thread per stream
@@ -1398,7 +1402,7 @@ __device__ __forceinline__ void sweep_tile_smc(const SweepArgs &a, int wave, uin
     }
     tile_finish<CW, DM>(a, BT ? wave * 16 + (int)(threadIdx.x >> 6) : wave, T.sys, cell_off, v, dcur, agg_keys, agg_vals,
                         active && ((acc0 && nc0 != old0) || u0 != t0), c0, f0, t0, u0,
-                        has1 && ((acc1 && nc1 != old1) || u1 != t1), c1, f1, t1, u1, acc0, acc1, active && bad);
+                        has1 && ((acc1 && nc1 != old1) || u1 != t1), c1, f1, t1, u1, acc0, acc1, active && bad, 0ull);
 }
 
 // The sweep kernel: one launch per sweep for every system.  With one tile
@@ -1464,23 +1468,27 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a)
     } else {
         // block tiles: the test is uniform over the block, so every thread
         // of a working block reaches the barriers of the tile
+        // the tile's acceptance count is read with its positions (see
+        // counts_per_tile; a.acc_tile is null for the other kernels)
         if constexpr (ST) {
             if (wave < a.n_ptiles) {
                 Bead b0, b1;
                 uint32_t clog;
                 stream_load(a, wave, s, b0, b1, clog);
+                const unsigned long long accp = a.acc_tile ? a.acc_tile[wave] : 0ull;
                 agg_clear<SLOTS>(agg_keys, agg_vals);
-                sweep_tile_stream<R, CW, DM>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog);
+                sweep_tile_stream<R, CW, DM>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog, accp);
             }
         } else if (wave < (BT ? a.n_ptiles : a.n_tiles)) {
             Bead b0, b1;
             uint32_t clog;
             tile_load<BT>(a, wave, b0, b1, clog);
+            const unsigned long long accp = !BT && a.acc_tile ? a.acc_tile[wave] : 0ull;
             agg_clear<SLOTS>(agg_keys, agg_vals);
             if (SMC && a.systems[tile_table<BT>(a)[wave].sys].smc)
                 sweep_tile_smc<R, CW, DM, CPL, BT>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog);
             else
-                sweep_tile<R, CW, DM, CPL, BT>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog);
+                sweep_tile<R, CW, DM, CPL, BT>(a, wave, s, cin, dprev, dcur, agg_keys, agg_vals, b0, b1, clog, accp);
         }
     }
     if constexpr (FI) {
@@ -2343,16 +2351,19 @@ static void launch_sweep_d(const SweepArgs &a, int blocks, hipStream_t st)
     // kernels built without that code (fewer registers)
     // block tiles: one tile per block (never with conversion zones, whose
     // chain sums stay within a wave)
-    if (a.cpl) {
-        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, true, false>), g, b, lds, st, a);
-        else if (a.packed == 1) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true, true>), g, b, lds, st, a);
-        else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true, false>), g, b, lds, st, a);
+    // only the plain and stream kernels count acceptances per tile
+    SweepArgs o = a;
+    if (!counts_per_tile(a)) o.acc_tile = nullptr;
+    if (o.cpl) {
+        if (o.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, true, false>), g, b, lds, st, o);
+        else if (o.packed == 1) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true, true>), g, b, lds, st, o);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, true, false>), g, b, lds, st, o);
     } else {
-        if (a.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, false, false>), g, b, lds, st, a);
-        else if (a.packed == 1) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, true>), g, b, lds, st, a);
-        else if (!SMC && a.packed == 2) hipLaunchKernelGGL((k_sweep_stream<R, CW, DM>), g, b, lds, st, a);
-        else if (!SMC) hipLaunchKernelGGL((k_sweep_plain<R, CW, DM>), g, b, lds, st, a);
-        else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, false>), g, b, lds, st, a);
+        if (o.max_blocks > 0) hipLaunchKernelGGL((k_sweep<R, CW, true, DM, SMC, false, false>), g, b, lds, st, o);
+        else if (o.packed == 1) hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, true>), g, b, lds, st, o);
+        else if (!SMC && o.packed == 2) hipLaunchKernelGGL((k_sweep_stream<R, CW, DM>), g, b, lds, st, o);
+        else if (!SMC) hipLaunchKernelGGL((k_sweep_plain<R, CW, DM>), g, b, lds, st, o);
+        else hipLaunchKernelGGL((k_sweep<R, CW, false, DM, SMC, false, false>), g, b, lds, st, o);
     }
 }
 
@@ -2466,6 +2477,27 @@ hipError_t launch_stream_halo(int repr, const HaloArgs &a, hipStream_t st)
         hipLaunchKernelGGL((k_stream_halo<BeadF32>), dim3(blocks), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((k_stream_halo<BeadCell>), dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_acc_fold(const Tile *tiles, int n_tiles, int stream,
+                                                  unsigned long long *acc_tile, unsigned long long *accept)
+{
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= n_tiles) return;
+    const unsigned long long v = acc_tile[t];
+    if (v == 0ull) return;
+    const uint32_t sys = stream ? stile_sys(tiles[t]) : tiles[t].sys;
+    atomicAdd(accept + ((int64_t)sys * kAcceptSlots + (t % kAcceptSlots)) * kAcceptStride, v);
+    acc_tile[t] = 0ull;
+}
+
+hipError_t launch_acc_fold(const Tile *tiles, int n_tiles, bool stream, unsigned long long *acc_tile,
+                           unsigned long long *accept, hipStream_t st)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_acc_fold, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, st, tiles, n_tiles,
+                       stream ? 1 : 0, acc_tile, accept);
     return hipGetLastError();
 }
 

@@ -47,7 +47,20 @@ struct SweepArgs {
     unsigned long long *conv;      // [n_sys][2]: chains converted to class a, to class b
     uint2 *halo;                   // stream tiles: boundary bead pairs, see halo_index
     int64_t halo_cap;              // stream tile entries per halo array
+    unsigned long long *acc_tile;  // accepted moves per tile (see counts_per_tile), or null
 };
+
+// The one-tile-per-wave kernels for uniform moves without coupling (wave
+// tiles and stream tiles) count accepted moves per tile: the wave that owns
+// tile t in a sweep reads acc_tile[t] with its positions and writes back the
+// sum after the moves, a plain load and store instead of a device atomic per
+// wave.  The host folds acc_tile into the per-system counters (and clears
+// it) before the tiling changes and before the counters are read; every
+// other kernel adds to the per-system counters with atomics.
+inline bool counts_per_tile(const SweepArgs &a)
+{
+    return !a.cpl && !a.smc && a.max_blocks == 0 && a.packed != 1;
+}
 
 // Stream tiles read the bead pairs of their two overlap lanes, which other
 // waves own and rewrite during the same sweep, from a copy taken before the
@@ -166,6 +179,10 @@ struct ObsArgs {
 
 hipError_t launch_sweep(int repr, int cw, const SweepArgs &a, hipStream_t st);
 hipError_t launch_stream_halo(int repr, const HaloArgs &a, hipStream_t st);
+// Add acc_tile[t] to the acceptance counters of tile t's system and clear it
+// (stream: the tiles are stream tiles, whose system is the low 24 bits).
+hipError_t launch_acc_fold(const Tile *tiles, int n_tiles, bool stream, unsigned long long *acc_tile,
+                           unsigned long long *accept, hipStream_t st);
 hipError_t launch_density(int repr, int cw, const DensityArgs &a, hipStream_t st);
 hipError_t launch_fields(int cw, const FieldArgs &a, hipStream_t st);
 hipError_t launch_unpack_counts(int cw, const uint32_t *counts, int64_t cell_off, int64_t n_cells,

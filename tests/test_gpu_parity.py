@@ -262,6 +262,37 @@ def test_stream_tiles_refresh_the_halo_after_new_positions():
     h.close()
 
 
+def test_acceptance_counts_across_tilings_and_reads():
+    """Wave- and stream-tile sweeps count accepted moves per tile and fold
+    them into the per-system counters before the tiling changes or the
+    counters are read; block tiles count with device atomics.  Contexts that
+    read their observables between sweeps, switch tilings through the
+    autotuner and sweep on must count exactly what a block-tile context
+    counts over the same trajectory."""
+    systems = stream_systems()
+    ref = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, density_mode=3, packed_tiles=1,
+               waves_per_block=4)
+    ref.sweep(9)
+    want = [ref.observables(k)["n_accepted"] for k in range(len(systems))]
+    assert all(w > 0 for w in want)
+    for pk in (0, 2):
+        tune_cache_clear()
+        g = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, density_mode=3, packed_tiles=pk,
+                 waves_per_block=4)
+        g.sweep(3)
+        mid = [g.observables(k)["n_accepted"] for k in range(len(systems))]
+        g.sweep(2)
+        t = g.autotune(1)
+        g.sweep(4)
+        got = [g.observables(k)["n_accepted"] for k in range(len(systems))]
+        print(f"[acceptance] start tiling {pk}, tuned to {t['packed_tiles']}: {got[:3]} vs {want[:3]}")
+        assert got == want, (pk, t)
+        assert all(0 < m < w for m, w in zip(mid, want))
+        assert _same_state(g.state(0), ref.state(0))
+        g.close()
+    ref.close()
+
+
 def test_stream_tiles_fall_back_with_smart_moves():
     """Stream tiles are asked for but the context moves with smart moves: the
     shape reports wave tiles and the sweep matches a wave-tile context."""
