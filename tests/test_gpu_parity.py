@@ -470,7 +470,10 @@ def test_checkpoint_resume_bit_exact(r, dm):
     """A checkpoint taken in one density mode resumes bit-exactly in another."""
     systems = W.batched_mixed(n_systems=3, seed=48, bead_range=(2000, 8000))
     a = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=dm)
-    a.sweep(6)
+    a.sweep(3)
+    acc3 = [a.observables(k)["n_accepted"] for k in range(len(systems))]
+    a.sweep(3)
+    acc6 = [a.observables(k)["n_accepted"] for k in range(len(systems))]
     b = Soma(systems, seed=SEED, pos_repr=r, count_width=16, density_mode=(dm + 1) % 4)
     b.sweep(3)
     saved = [b.state(k) for k in range(len(systems))]
@@ -487,6 +490,8 @@ def test_checkpoint_resume_bit_exact(r, dm):
         # acceptance counts the three sweeps run on the resumed context
         oc = c.observables(k)
         assert oc["n_moves"] == 3 * sysd.n_beads and oc["sweep"] == 6
+        assert oc["n_accepted"] == acc6[k] - acc3[k]
+        assert oc["accept_ratio"] == (acc6[k] - acc3[k]) / (3 * sysd.n_beads)
         assert 0.3 < oc["accept_ratio"] < 1.0
     for k in range(len(systems)):
         sa, sc = a.state(k), c.state(k)
