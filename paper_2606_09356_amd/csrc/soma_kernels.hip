@@ -17,16 +17,22 @@
 //   * The fields are never stored: omega of a cell is an affine function of
 //     its two counts, evaluated where a moved bead needs it (only when the
 //     trial move leaves the bead's cell).
-//   * The density is updated, not rebuilt: a sweep reads the counts C
-//     (frozen, for the fields) and adds -1/+1 atomically to a delta D only
-//     for accepted moves that change cell (about 0.2 of the beads), not one
-//     atomic per bead; a wave first merges its updates in LDS, which removes
-//     about a fifth of them.  Two placements of the fold C += D, D = 0:
-//     a short streaming kernel after each sweep, or the next sweep's own
-//     threads: sweep s then reads its counts as B[s-1] + D[s-1], writes
-//     B[s] = B[s-1] + D[s-1], adds its changes to D[s] and clears D[s+1]
-//     (two base and three delta buffers in rotation), so the fold traffic
-//     overlaps the move work.
+//   * The density is updated, not rebuilt: a sweep reads frozen counts (for
+//     the fields) and adds -1/+1 atomically only for accepted moves that
+//     change cell (about a fifth of the beads), not one atomic per bead; a
+//     wave first merges its updates in LDS.  Four placements of those
+//     atomics (density modes): a delta folded by a streaming kernel after
+//     the sweep (0); a delta folded by the next sweep's own threads, which
+//     read B[s-1] + D[s-1] (1); face fluxes, folded as their divergence
+//     (2); or the second of two identical count buffers, which no gather of
+//     the sweep reads, copied back afterwards (3).
+//   * Tilings: wave tiles (whole chains on the lanes of one wave), block
+//     tiles (whole chains packed over the waves of a workgroup) and stream
+//     tiles (a system's lanes in chain order, 62 owned lanes per wave plus
+//     two overlap lanes whose pairs come from a halo copy).
+//   * Accepted moves are counted per tile by the wave- and stream-tile
+//     kernels (a plain load and store per wave), per system with one atomic
+//     per wave by the others.
 //   * Philox4x32-10 is counter based: one 128-bit block per (bead, logical
 //     chain, sweep, system); no RNG state lives in memory.
 //   * Per system, the trial move is uniform in a cube or bond-force biased
@@ -700,7 +706,7 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) { return fmaf(a.x, b.x
 __device__ __forceinline__ float3 add3(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
 
 // ---------------------------------------------------------------------------
-// The sweep kernel: even pass, odd pass, density delta (and, in density
+// The sweep kernel: even pass, odd pass, density update (and, in density
 // mode 1, the fold of the previous delta).  One launch per sweep for every
 // system.
 // ---------------------------------------------------------------------------
@@ -769,13 +775,14 @@ __device__ __forceinline__ void emit_faces(uint32_t *keys, uint32_t *vals, int64
     }
 }
 
-// End of a wave tile: the density delta of the beads whose (cell, type)
-// changed -- cell words (density modes 0, 1) or face fluxes (mode 2) --
+// End of a tile: the density change of the beads whose (cell, type)
+// changed -- cell words (density modes 0, 1, 3) or face fluxes (mode 2) --
 // merged per wave in LDS, then one device atomic per distinct word with a
-// nonzero sum; the acceptance count and the cell-range status.  Bead j moved
-// from cell o_j with type t_j to cell f_j with type u_j (u_j != t_j only
-// for a chain converted in a boundary zone, never in mode 2); m_j says that
-// something changed.
+// nonzero sum; the acceptance count (into the tile's own counter when
+// a.acc_tile is set: acc_prev + this sweep's count) and the cell-range
+// status.  Bead j moved from cell o_j with type t_j to cell f_j with type u_j
+// (u_j != t_j only for a chain converted in a boundary zone, never in mode
+// 2); m_j says that something changed.
 template <int CW, int DM>
 __device__ __forceinline__ void tile_finish(const SweepArgs &a, int wave, uint32_t sys, int64_t cell_off,
                                             const SysView &v, uint32_t *dcur, uint32_t *agg_keys,
