@@ -168,6 +168,21 @@ def run_workload(name, steps, warmup, shape=None, autotune=True, runs=RUNS, kern
         g.sweep(max(warmup, 5))
         g.sync()
         res["kernel_us"] = g.time_kernels(5)
+        # the K timed sweeps hold no chain reorder when K is below the
+        # reorder interval R; one call of R sweeps holds exactly one, so its
+        # time per sweep includes the reorder's share
+        R = W.WORKLOAD_OPTIONS[name]["reorder_every"]
+        if R > 0:
+            import torch
+            g.sync()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(g.stream)
+            g.sweep(R)
+            e1.record(g.stream)
+            e1.synchronize()
+            res["reorder_every"] = R
+            res["sweep_us_with_reorder"] = e0.elapsed_time(e1) * 1e3 / R
     g.close()
     return res
 
@@ -347,6 +362,12 @@ def main():
         "roofline": roofline_of(main_res, prof),
         "observables_system0": {k: main_res["obs0"][k] for k in ("Re2", "Re2_err", "Rg2", "Ebond_per_chain",
                                                                   "Enb_per_chain", "accept_ratio")},
+        "with_chain_reorder": ({"reorder_every": main_res["reorder_every"],
+                                "sweep_us": main_res["sweep_us_with_reorder"],
+                                "moves_per_s": B / (main_res["sweep_us_with_reorder"] * 1e-6),
+                                "note": "one call of reorder_every sweeps, holding one spatial chain reorder "
+                                        "(the timed runs of K < reorder_every sweeps hold none)"}
+                               if "sweep_us_with_reorder" in main_res else None),
         "timed_runs_s": main_res["runs_s"],
         "paper_soma": PAPER_SOMA,
     }
