@@ -72,7 +72,7 @@ PAPER_SOMA = {
 }
 
 
-def survey_bytes_per_move(pos_repr, count_width):
+def model_bytes_per_move(pos_repr, count_width):
     """Algorithmic HBM bytes per bead move: positions read and written
     (12 or 24 B each way), the field read once per cell (8 B per cell), the
     count written (4 or 8 B per cell), the field kernel's count read and its
@@ -191,7 +191,7 @@ def run_workload(name, steps, warmup, shape=None, autotune=True, runs=RUNS, kern
 
 
 def roofline_of(res, prof=None):
-    bpm = survey_bytes_per_move(res["pos_repr"], res["count_width"])
+    bpm = model_bytes_per_move(res["pos_repr"], res["count_width"])
     per_sweep = bpm * res["beads"]
     achieved = per_sweep / (res["sweep_us"] * 1e-6) / 1e9
     r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
