@@ -25,7 +25,7 @@ chains, 8192 beads) at 1000 sweeps, the 16.8M-bead mixed-precision system, the 6
 uneven systems against the same systems run one after another, and the
 bond-force-biased (smart) move workload.
 
-Roofline: algorithmic bytes per bead move from the hot-path scope table
+Roofline: algorithmic bytes per bead move of the sweep's data model
 (positions read and written, field read, count write, field-kernel count
 read and field write: 36 B for FP32 positions with packed uint16 counts, 60 B
 for cell + offset with uint16, 64 B for cell + offset with uint32) times the
