@@ -71,6 +71,17 @@ def test_invalid_descriptors_are_rejected(lib, field, value):
     assert lib.soma_last_error(None)
 
 
+def test_empty_batches_and_null_arguments_are_rejected(lib):
+    """No systems, a null descriptor array or a null size pointer: EINVAL
+    with a message, before anything touches a GPU."""
+    arr, keep = S._desc_array(W.plain_small())
+    n = C.c_size_t(0)
+    assert lib.soma_workspace_size(arr, 0, C.byref(_opts()), C.byref(n)) == S.SOMA_EINVAL
+    assert lib.soma_last_error(None)
+    assert lib.soma_workspace_size(None, 1, C.byref(_opts()), C.byref(n)) == S.SOMA_EINVAL
+    assert lib.soma_workspace_size(arr, 1, C.byref(_opts()), None) == S.SOMA_EINVAL
+
+
 def test_invalid_options_are_rejected(lib):
     arr, keep = S._desc_array(W.plain_small())
     n = C.c_size_t(0)

@@ -309,6 +309,26 @@ def test_stream_tiles_fall_back_with_smart_moves():
     h.close()
 
 
+def test_zero_sweeps_change_nothing_and_negative_counts_are_rejected():
+    """soma_mc_sweep(0) is a no-op in every tiling (state, density, sweep
+    and move counters unchanged); a negative count is SOMA_EINVAL."""
+    systems = stream_systems()[:3]
+    for pk in (0, 1, 2):
+        g = Soma(systems, seed=SEED, pos_repr="cell", count_width=16, density_mode=3, packed_tiles=pk,
+                 waves_per_block=4)
+        g.sweep(2)
+        before = [(g.state(k), g.density(k), g.observables(k)) for k in range(len(systems))]
+        g.sweep(0)
+        for k, (st, dens, ob) in enumerate(before):
+            assert _same_state(g.state(k), st) and (g.density(k) == dens).all()
+            after = g.observables(k)
+            assert (after["sweep"], after["n_moves"], after["n_accepted"]) == (ob["sweep"], ob["n_moves"],
+                                                                             ob["n_accepted"])
+        with pytest.raises(SomaError):
+            g.sweep(-1)
+        g.close()
+
+
 def test_accept_counter_matches_oracle():
     systems = W.batched_uneven(n_systems=4, seed=44, chain_range=(100, 400))
     g, orcs = make_pair(systems, "f32", 16)
