@@ -118,6 +118,7 @@ struct soma_ctx {
     // which tile table indexes the counts pending in acc_tile: -1 none (all
     // zero), 0 wave tiles, 2 stream tiles
     int acc_kind = -1;
+    int pos_swap = 0;      // 1: the positions live in the buffers laid out as Q, D
     int any_smc = 0;       // some system moves with bond-force-biased moves
     int any_zones = 0;     // some system has conversion zones (density mode 2 excluded)
     uint64_t sweep = 0;
@@ -133,10 +134,18 @@ struct soma_ctx {
     DevSys *d_sys() const { return reinterpret_cast<DevSys *>(ws + L.systems); }
     Tile *d_tiles() const { return reinterpret_cast<Tile *>(ws + L.tiles); }
     Tile *d_ptiles() const { return reinterpret_cast<Tile *>(ws + L.ptiles); }
-    float *P(int d) const { return reinterpret_cast<float *>(ws + L.P[d]); }
-    int *C(int d) const { return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + L.C[d]) : nullptr; }
-    float *Q(int d) const { return reinterpret_cast<float *>(ws + L.Q[d]); }
-    int *D(int d) const { return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + L.D[d]) : nullptr; }
+    // positions (P, C) and their scratch of the same layout (Q, D); a chain
+    // reorder permutes into the scratch and swaps the two roles
+    float *P(int d) const { return reinterpret_cast<float *>(ws + (pos_swap ? L.Q[d] : L.P[d])); }
+    int *C(int d) const
+    {
+        return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + (pos_swap ? L.D[d] : L.C[d])) : nullptr;
+    }
+    float *Q(int d) const { return reinterpret_cast<float *>(ws + (pos_swap ? L.P[d] : L.Q[d])); }
+    int *D(int d) const
+    {
+        return repr == soma::REPR_CELL ? reinterpret_cast<int *>(ws + (pos_swap ? L.C[d] : L.D[d])) : nullptr;
+    }
     uint32_t *chain_id() const { return reinterpret_cast<uint32_t *>(ws + L.chain_id); }
     uint32_t *u32(size_t off) const { return reinterpret_cast<uint32_t *>(ws + off); }
     // Count buffers base[0..1] and delta buffers delta[0..2], count_words each.
@@ -822,12 +831,9 @@ int reorder_chains(soma_ctx *c)
 {
     const soma::ReorderArgs r = reorder_args(c);
     HIPCHK(c, soma::launch_reorder(c->repr, r, c->stream));
-    const size_t n = sizeof(float) * (size_t)c->L.total_slots;
-    for (int d = 0; d < 3; ++d) {
-        HIPCHK(c, hipMemcpyAsync(c->P(d), c->Q(d), n, hipMemcpyDeviceToDevice, c->stream));
-        if (c->repr == soma::REPR_CELL)
-            HIPCHK(c, hipMemcpyAsync(c->C(d), c->D(d), n, hipMemcpyDeviceToDevice, c->stream));
-    }
+    // the permuted positions are in the scratch: swap the roles instead of
+    // copying them back (graphs are cached per role, see graph_for)
+    c->pos_swap ^= 1;
     HIPCHK(c, hipMemcpyAsync(c->chain_id(), r.chain_id2, sizeof(uint32_t) * (size_t)c->L.total_chains,
                              hipMemcpyDeviceToDevice, c->stream));
     c->last_reorder = c->sweep;
@@ -884,7 +890,9 @@ constexpr int kGraphChunk = 256;
 
 int graph_for(soma_ctx *c, int32_t n, hipGraphExec_t *out)
 {
-    auto it = c->graphs.find(n);
+    // the kernel nodes hold the position buffers: one graph per role
+    const int key = 2 * n + c->pos_swap;
+    auto it = c->graphs.find(key);
     if (it != c->graphs.end()) { *out = it->second; return SOMA_OK; }
     if (!c->capture_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
@@ -896,7 +904,7 @@ int graph_for(soma_ctx *c, int32_t n, hipGraphExec_t *out)
     hipGraphExec_t ex = nullptr;
     HIPCHK(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
     c->graph_defs.push_back(g);
-    c->graphs[n] = ex;
+    c->graphs[key] = ex;
     *out = ex;
     return SOMA_OK;
 }
